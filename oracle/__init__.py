@@ -1,0 +1,174 @@
+"""CPU oracle for the LexBFS chordality test -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never loads it and
+shares no code with it.
+
+The arithmetic lives in ``oracle.c`` (plain sequential C, built with gcc):
+
+* :func:`lexbfs`      -- partition-refinement LexBFS (Section 4.2) with the
+  smallest-id tie-break; returns order, rank and the parent p(v).
+* :func:`peo`         -- the parent-based perfect-elimination test
+  (Section 5.2 box), every failing vertex and the canonical witness.
+* :func:`certificate` -- the canonical chordless cycle (project rule; its
+  parity is pinned by invariants and brute force, not by the paper).
+* :func:`chordal_test` -- all three for one graph.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    lib.oracle_lexbfs.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p]
+    lib.oracle_peo.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p]
+    lib.oracle_certificate.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, i32p, i32p, i32p]
+    lib.oracle_chordal_test.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, ct=ctypes.c_int32):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    return rp, ci
+
+
+@dataclass
+class OrderResult:
+    order: np.ndarray
+    rank: np.ndarray
+    parent: np.ndarray
+
+
+@dataclass
+class PeoResult:
+    is_peo: bool
+    p: np.ndarray
+    fail: np.ndarray
+    witness: tuple  # (v*, x*, z*) or (-1, -1, -1)
+
+
+@dataclass
+class TestResult:
+    chordal: bool
+    witness: tuple
+    cycle: np.ndarray  # empty when chordal
+    fallback: bool
+    order: np.ndarray
+    rank: np.ndarray
+    parent: np.ndarray
+
+
+def lexbfs(g) -> OrderResult:
+    n = g.n
+    rp, ci = _csr(g)
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    rank = np.zeros(max(n, 1), dtype=np.int32)
+    parent = np.zeros(max(n, 1), dtype=np.int32)
+    rc = _load().oracle_lexbfs(n, _p(rp), _p(ci), _p(order), _p(rank), _p(parent))
+    if rc != 0:
+        raise RuntimeError(f"oracle_lexbfs failed ({rc})")
+    return OrderResult(order[:n], rank[:n], parent[:n])
+
+
+def peo(g, rank: np.ndarray) -> PeoResult:
+    n = g.n
+    rp, ci = _csr(g)
+    rk = np.ascontiguousarray(rank, dtype=np.int32)
+    if rk.size == 0:
+        rk = np.zeros(1, dtype=np.int32)
+    p = np.zeros(max(n, 1), dtype=np.int32)
+    fail = np.zeros(max(n, 1), dtype=np.uint8)
+    w = np.full(3, -1, dtype=np.int32)
+    rc = _load().oracle_peo(n, _p(rp), _p(ci), _p(rk), _p(p), _p(fail, ctypes.c_uint8), _p(w))
+    if rc < 0:
+        raise RuntimeError(f"oracle_peo failed ({rc})")
+    return PeoResult(rc == 1, p[:n], fail[:n].astype(bool), tuple(int(x) for x in w))
+
+
+def certificate(g, order, rank, witness, force_fallback: bool = False):
+    """Returns (cycle array, used_fallback)."""
+    n = g.n
+    rp, ci = _csr(g)
+    cyc = np.zeros(max(n, 1), dtype=np.int32)
+    ln = np.zeros(1, dtype=np.int32)
+    fb = np.zeros(1, dtype=np.int32)
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    r = np.ascontiguousarray(rank, dtype=np.int32)
+    v, x, z = witness
+    rc = _load().oracle_certificate(n, _p(rp), _p(ci), _p(o), _p(r), v, x, z, int(force_fallback), _p(cyc), _p(ln), _p(fb))
+    if rc != 0:
+        raise RuntimeError(f"oracle_certificate failed ({rc}): no chordless cycle found")
+    return cyc[: int(ln[0])].copy(), bool(fb[0])
+
+
+def chordal_test(g) -> TestResult:
+    n = g.n
+    rp, ci = _csr(g)
+    m = max(n, 1)
+    order = np.zeros(m, dtype=np.int32)
+    rank = np.zeros(m, dtype=np.int32)
+    parent = np.zeros(m, dtype=np.int32)
+    cyc = np.zeros(m, dtype=np.int32)
+    res = np.zeros(6, dtype=np.int32)
+    rc = _load().oracle_chordal_test(n, _p(rp), _p(ci), _p(order), _p(rank), _p(parent), _p(cyc), _p(res))
+    if rc != 0:
+        raise RuntimeError(f"oracle_chordal_test failed ({rc})")
+    return TestResult(bool(res[0]), (int(res[1]), int(res[2]), int(res[3])), cyc[: int(res[4])].copy(),
+                      bool(res[5]), order[:n], rank[:n], parent[:n])
+
+
+class use_library:
+    """Context manager: route this module's calls to another build of
+    oracle.c (tests use it to check that planted mistakes are caught)."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.saved = None
+
+    def __enter__(self):
+        global _lib, _LIB_PATH
+        self.saved = (_lib, _LIB_PATH)
+        _lib, _LIB_PATH = None, self.path
+        _load()
+        return self
+
+    def __exit__(self, *exc):
+        global _lib, _LIB_PATH
+        _lib, _LIB_PATH = self.saved
+        return False
