@@ -299,4 +299,11 @@ def config_batch(count: int = 4096, lo: int = 32, hi: int = 4096, seed: int = 0)
     """Batch mix: N log-uniform on [lo, hi]; 50% SUBTREE, 25% GNP with average
     degree 8, 25% SUBTREE with a planted chordless cycle of length in [4, 12]."""
     ns, kinds, Ls, _ = mix_specs(count, lo, hi, seed)
-    return [mix_graph(int(ns[i]), int(kinds[i]), int(Ls[i]), graph_seed(seed, 1000 + i)) for i in range(count)]
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
+        return mix_graph(int(ns[i]), int(kinds[i]), int(Ls[i]), graph_seed(seed, 1000 + i))
+
+    # the C generators release the GIL; results are independent of the pool
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(count)))

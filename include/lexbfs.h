@@ -1,0 +1,178 @@
+/*
+ * lexbfs.h -- C ABI of the MI355X (gfx950) chordality library.
+ *
+ * The library computes, on the GPU, the two steps of the chordality test of
+ * Lupinska, "A Parallel Algorithm to Test Chordality of Graphs":
+ *   1. a Lexicographic BFS order (Section 4.1 definition: every step numbers
+ *      the unnumbered vertex with the lexicographically largest label and
+ *      appends a strictly decreasing number to the labels of its unnumbered
+ *      neighbours; the parallel form is Section 6.1), and
+ *   2. the perfect-elimination test of that order (Section 5.2, parallel form
+ *      Section 6.2): with p(v) the latest-ordered earlier neighbour of v, the
+ *      graph is chordal iff LN(v) \ {p(v)} is a subset of N(p(v)) for every v
+ *      (Theorem 5.1 and the argument of Section 5.3).
+ *
+ * Conventions shared by every entry point
+ *   - Vertex ids are 0-based. order[i] is the vertex numbered at step i (the
+ *     paper's pi(i+1)); rank[v] is its inverse; parent[v] = p(v) or -1.
+ *   - Ties between equal labels go to the smallest vertex id, at every step
+ *     (so the first vertex is 0, the paper's vertex 1). The paper leaves the
+ *     choice open ("we cannot predict which one", Section 6.1); fixing it
+ *     makes every output unique and reproducible.
+ *   - A graph is given twice, in the same vertex ids: an int32 CSR (rows
+ *     strictly ascending, symmetric, no self-loops) and an n x n adjacency
+ *     bitset (row v at bits + v*words_per_row, bit u in word u>>6 at position
+ *     u&63, LSB first; zero diagonal; bits >= n in the last word are zero).
+ *     The paper keeps the graph as an n x n boolean matrix (Section 6.3); the
+ *     bitset is that matrix packed 64 entries per word.
+ *   - Unless stated otherwise every pointer is DEVICE memory owned by the
+ *     caller. Inputs are never written. Nothing is allocated on the calls'
+ *     path: scratch lives in the caller's workspace `ws` (device memory,
+ *     256-byte aligned, size from the matching *_workspace_bytes function).
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream); outputs are valid once the stream has reached the call. The
+ *     return value only reports argument errors and launch failures.
+ *   - Calls are re-entrant as long as concurrent calls use distinct
+ *     workspaces and outputs.
+ */
+#ifndef LEXBFS_H
+#define LEXBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define LEXBFS_OK 0
+#define LEXBFS_EINVAL (-1)  /* null required pointer, n < 0, words_per_row < ceil(n/64), nnz outside [0, 2^31) */
+#define LEXBFS_ENOWS (-2)   /* workspace pointer null or smaller than required */
+#define LEXBFS_EHIP (-3)    /* a HIP runtime call or kernel launch failed */
+#define LEXBFS_EGRAPH (-4)  /* reserved: input contract violation detected by a validating call */
+#define LEXBFS_ETOOBIG (-5) /* n above LEXBFS_MAX_N or above what the device's LDS supports */
+
+/* Largest supported vertex count: class ids and vertex ids are kept in 16 bits. */
+#define LEXBFS_MAX_N 65536
+
+/* Flags for chordal_test / chordal_test_batch. */
+#define LEXBFS_FLAG_FORCE_FALLBACK 0x1u /* build the certificate with the fallback rule only (test hook) */
+
+/* One graph. All pointers are device memory. */
+typedef struct lexbfs_graph {
+    int32_t n;                /* number of vertices, 0 <= n <= LEXBFS_MAX_N */
+    int32_t reserved;         /* must be 0 */
+    int64_t nnz;              /* CSR entries = 2|E|, 0 <= nnz < 2^31 */
+    const int32_t *row_ptr;   /* [n+1] */
+    const int32_t *col_idx;   /* [nnz], strictly ascending within each row */
+    const uint64_t *bits;     /* [n * words_per_row] */
+    int64_t words_per_row;    /* row stride in 64-bit words, >= ceil(n/64) */
+} lexbfs_graph_t;
+
+/* Verdict for one graph, written to device memory (32 bytes).
+ * chordal = 1: the LexBFS order is a perfect elimination order (Theorem 5.1);
+ *   witness_* = -1, cycle_len = 0.
+ * chordal = 0: witness_v = v*, the failing vertex of smallest rank (also the
+ *   first vertex whose left neighbourhood is not a clique, Section 5.3);
+ *   witness_p = x* = p(v*); witness_z = z*, the smallest-rank vertex of
+ *   LN(v*) \ {x*} not adjacent to x*. cycle_len >= 4 is the length of the
+ *   chordless cycle written to the cycle output (see chordal_test).
+ * fallback = 1 when the certificate came from the fallback rule. */
+typedef struct lexbfs_result {
+    int32_t chordal;
+    int32_t witness_v;
+    int32_t witness_p;
+    int32_t witness_z;
+    int32_t cycle_len;
+    int32_t fallback;
+    int32_t reserved[2];
+} lexbfs_result_t;
+
+/* Optional per-graph outputs, device pointers each of [n] int32, or NULL to
+ * keep them in the workspace. */
+typedef struct lexbfs_outputs {
+    int32_t *order;
+    int32_t *rank;
+    int32_t *parent;
+    int32_t *cycle;
+} lexbfs_outputs_t;
+
+/* Workspace bytes for lexbfs_order / chordal_test on a graph of n vertices. */
+size_t lexbfs_workspace_bytes(int32_t n);
+
+/*
+ * lexbfs_order -- the LexBFS order (Section 4.1 definition; Section 6.1
+ * parallel algorithm, here one persistent kernel instead of four launches
+ * per step) together with its inverse and the parent p(v) of Section 5.2.
+ *   g       graph (device pointers inside a host struct)
+ *   order   [n] out, required
+ *   rank    [n] out or NULL
+ *   parent  [n] out or NULL
+ * Errors: LEXBFS_EINVAL, LEXBFS_ENOWS, LEXBFS_ETOOBIG, LEXBFS_EHIP.
+ */
+int lexbfs_order(const lexbfs_graph_t *g, int32_t *order, int32_t *rank, int32_t *parent,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * chordal_test -- LexBFS order, then the parent-based perfect-elimination
+ * test (Section 6.2), then for a non-chordal graph the witness and a
+ * chordless cycle of length >= 4 (not in the paper; defined as follows).
+ * With A = (V \ N[v*]) + {x*, z*}: a breadth-first search inside A from x*
+ * reaches z* at distance d; walking back from z*, each vertex's predecessor
+ * is the smallest-id vertex of the previous layer adjacent to it. The cycle
+ * is [v*, x*, ..., z*]. If z* is unreachable (or FORCE_FALLBACK is set), the
+ * first triple (v, a, b) with v by ascending rank, a, b in LN(v) not
+ * adjacent, rank a < rank b, ordered by (rank a, rank b), whose b reaches a
+ * inside (V \ N[v]) + {a, b} gives [v, b, ..., a] by the same rule.
+ *   res  [1] out, required
+ *   out  host struct of optional device outputs, or NULL
+ * Errors: as lexbfs_order.
+ */
+int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_outputs_t *out,
+                 void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/* Schedule for chordal_test_batch. A graph with n <= wave_max_n is run by
+ * one 64-lane wavefront; a larger one by a whole workgroup of
+ * block_threads lanes. lds_bytes is the dynamic LDS per workgroup
+ * (0 = derived from the largest graph). */
+typedef struct lexbfs_tuning {
+    int32_t wave_max_n;
+    int32_t block_threads;   /* 256 or 1024 */
+    int32_t lds_bytes;
+    int32_t reserved;
+} lexbfs_tuning_t;
+
+/* Workspace bytes for chordal_test_batch over these graphs (host array). */
+size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count);
+
+/*
+ * chordal_test_batch -- chordal_test on `count` independent graphs in one
+ * pass: one persistent LexBFS launch over a longest-first work queue (a
+ * graph per wavefront or per workgroup as the tuning says), one sweep
+ * launch, one certificate launch.
+ *   gs      HOST array [count] of graph descriptors (device pointers)
+ *   outs    HOST array [count] of optional outputs, or NULL
+ *   res     DEVICE array [count] of results
+ *   tuning  HOST pointer or NULL for the built-in schedule
+ * The per-graph descriptor table is staged into the workspace with a
+ * host-to-device copy on `stream`; the calling thread returns once the
+ * table has been staged. Every graph needs n <= LEXBFS_MAX_N and must fit
+ * the workgroup's LDS (n <= 16384 with the built-in schedule).
+ * Errors: as chordal_test; LEXBFS_ETOOBIG names a graph beyond the limit.
+ */
+int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
+                       lexbfs_result_t *res, const lexbfs_tuning_t *tuning,
+                       void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/* Short English description of a return code (static storage). */
+const char *lexbfs_strerror(int code);
+
+/* Library ABI version (incremented on incompatible changes). */
+int lexbfs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEXBFS_H */

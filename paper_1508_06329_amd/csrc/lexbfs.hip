@@ -1,0 +1,741 @@
+// lexbfs.hip -- kernels and C ABI of the gfx950 chordality library.
+//
+// Path per graph (Lupinska, "A Parallel Algorithm to Test Chordality of
+// Graphs"): LexBFS order (Section 6.1) -> parent-based perfect-elimination
+// sweep (Section 6.2) -> witness and chordless-cycle certificate.
+// The device-side state machine of LexBFS is described in lexbfs_device.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "lexbfs.h"
+#include "lexbfs_device.h"
+
+using namespace lxd;
+
+namespace {
+
+constexpr int kAbiVersion = 1;
+constexpr size_t kAlign = 256;
+constexpr int kSweepThreads = 256;
+constexpr int kFinishThreads = 256;
+
+// Everything a kernel needs about one graph (device copy for batches).
+struct GDesc {
+    int32_t n;
+    int32_t wn;        // ceil(n / 64)
+    int64_t W;         // row stride in words
+    const int32_t *rp;
+    const int32_t *ci;
+    const uint64_t *bits;
+    int32_t *order;
+    int32_t *rank;
+    int32_t *parent;
+    int32_t *cycle;
+    int32_t *level;    // certificate scratch [n]
+    int32_t *q0;       // [n]
+    int32_t *q1;       // [n]
+    int32_t *lnbuf;    // [n]
+    uint32_t *failkey; // [1]
+    uint32_t *gtab;    // [2n] class tables in global memory (large n), else null
+    lexbfs_result_t *res;
+};
+
+struct SweepItem {
+    int32_t g;
+    int32_t r0;
+    int32_t r1;
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Block helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_sync_agent()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ int32_t cas_agent(int32_t *p, int32_t expected, int32_t desired)
+{
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return expected;
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t *row, int u) { return (row[u >> 6] >> (u & 63)) & 1ull; }
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// Block-wide min; every thread gets the result. s: LDS scratch of T/64 words.
+template <int T>
+__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t *s)
+{
+    v = wave_min_u32(v);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = s[0];
+#pragma unroll
+    for (int k = 1; k < T / kWave; ++k) r = min(r, s[k]);
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Certificate search: layered BFS from src inside A = (V \ N[c]) + {src, dst},
+// stopped after the layer that reaches dst; then back from dst, taking the
+// smallest-id neighbour of the previous layer each time. Writes
+// path[0] = src .. path[d] = dst and returns d + 1, or 0 if unreachable.
+// All threads of the block call it with the same arguments.
+// ---------------------------------------------------------------------------
+template <int T>
+__device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path)
+{
+    __shared__ int s_nq;
+    __shared__ int s_pred;
+    const int tid = threadIdx.x;
+    const uint64_t *rowc = g.bits + (int64_t)c * g.W;
+    for (int u = tid; u < g.n; u += T) g_store_i(&g.level[u], -1);
+    block_sync_agent();
+    if (tid == 0) {
+        g_store_i(&g.level[src], 0);
+        g_store_i(&g.q0[0], src);
+    }
+    block_sync_agent();
+    int qn = 1, d = 0;
+    int32_t *cur = g.q0, *nxt = g.q1;
+    const int wave = tid >> 6, lane = tid & 63;
+    while (qn > 0 && g_load_i(&g.level[dst]) < 0) {
+        if (tid == 0) s_nq = 0;
+        __syncthreads();
+        for (int f = wave; f < qn; f += T / kWave) {
+            const int u = g_load_i(&cur[f]);
+            const int e = g.rp[u + 1];
+            for (int j = g.rp[u] + lane; j < e; j += kWave) {
+                const int y = g.ci[j];
+                if ((unsigned)y >= (unsigned)g.n) continue;
+                const bool inA = (y == src) || (y == dst) || (y != c && !test_bit(rowc, y));
+                if (!inA || g_load_i(&g.level[y]) >= 0) continue;
+                if (cas_agent(&g.level[y], -1, d + 1) == -1) {
+                    const int pos = atomicAdd(&s_nq, 1);
+                    g_store_i(&nxt[pos], y);
+                }
+            }
+        }
+        block_sync_agent();
+        qn = s_nq;
+        int32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        ++d;
+        __syncthreads();
+    }
+    const int L = g_load_i(&g.level[dst]);
+    if (L < 0) return 0;
+    if (tid == 0) path[L] = dst;
+    int y = dst;
+    for (int l = L; l >= 1; --l) {
+        if (tid == 0) s_pred = INT_MAX;
+        __syncthreads();
+        const int e = g.rp[y + 1];
+        for (int j = g.rp[y] + tid; j < e; j += T) {  // rows ascend: first hit per lane is its minimum
+            const int u = g.ci[j];
+            if ((unsigned)u < (unsigned)g.n && g_load_i(&g.level[u]) == l - 1) {
+                atomicMin(&s_pred, u);
+                break;
+            }
+        }
+        __syncthreads();
+        y = s_pred;
+        __syncthreads();
+        if (y == INT_MAX) return 0;  // only with a non-symmetric CSR
+        if (tid == 0) path[l - 1] = y;
+    }
+    return L + 1;
+}
+
+// Witness and certificate for one graph; all threads of the block call it.
+template <int T>
+__device__ void finish_graph(const GDesc &g, uint32_t flags)
+{
+    __shared__ uint32_t s_red[T / kWave];
+    __shared__ uint32_t s_wcnt[T / kWave];
+    const int tid = threadIdx.x;
+    const uint32_t fk = g.n > 0 ? g_load(g.failkey) : kNoFail;
+    if (fk == kNoFail) {
+        if (tid == 0) {
+            lexbfs_result_t r;
+            r.chordal = 1;
+            r.witness_v = r.witness_p = r.witness_z = -1;
+            r.cycle_len = 0;
+            r.fallback = 0;
+            r.reserved[0] = r.reserved[1] = 0;
+            *g.res = r;
+        }
+        return;
+    }
+    const int v = g.order[fk];
+    const int x = g.parent[v];
+    const int rx = g.rank[x];
+    const uint64_t *rowv = g.bits + (int64_t)v * g.W;
+    const uint64_t *rowx = g.bits + (int64_t)x * g.W;
+    const uint64_t tail = (g.n & 63) ? ((1ull << (g.n & 63)) - 1ull) : ~0ull;
+    uint32_t best = UINT_MAX;
+    for (int w = tid; w < g.wn; w += T) {
+        for (uint64_t X = rowv[w] & ~rowx[w] & (w == g.wn - 1 ? tail : ~0ull); X; X &= X - 1) {
+            const int z = (w << 6) + ctz64(X);
+            const uint32_t rz = (uint32_t)g.rank[z];
+            if ((int)rz < rx) best = min(best, rz);
+        }
+    }
+    best = block_min_u32<T>(best, s_red);
+    if (best >= (uint32_t)g.n) {
+        // Only reachable when the input breaks its contract (e.g. an
+        // asymmetric bitset): report the failure without a certificate.
+        if (tid == 0) {
+            lexbfs_result_t r;
+            r.chordal = 0;
+            r.witness_v = v;
+            r.witness_p = x;
+            r.witness_z = -1;
+            r.cycle_len = 0;
+            r.fallback = 0;
+            r.reserved[0] = r.reserved[1] = 0;
+            *g.res = r;
+        }
+        return;
+    }
+    const int z = g.order[best];
+
+    int len = 0, fb = 0;
+    if (!(flags & LEXBFS_FLAG_FORCE_FALLBACK)) {
+        len = bfs_path<T>(g, v, x, z, g.cycle + 1);
+        if (len > 0) {
+            if (tid == 0) g.cycle[0] = v;
+            len += 1;
+        }
+    }
+    if (len == 0) {
+        fb = 1;
+        // Fallback: vertices by ascending rank, pairs of non-adjacent earlier
+        // neighbours by ascending (rank a, rank b).
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int rv = 0; rv < g.n && len == 0; ++rv) {
+            const int v2 = g.order[rv];
+            const uint64_t *row2 = g.bits + (int64_t)v2 * g.W;
+            int k = 0;
+            for (int base = 0; base < rv; base += T) {  // LN(v2) in rank order
+                const int r = base + tid;
+                const bool in = r < rv && test_bit(row2, g.order[r]);
+                const uint64_t bal = __ballot(in);
+                if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(bal);
+                __syncthreads();
+                int off = k, total = 0;
+                for (int w = 0; w < T / kWave; ++w) {
+                    if (w < wave) off += (int)s_wcnt[w];
+                    total += (int)s_wcnt[w];
+                }
+                if (in) g_store_i(&g.lnbuf[off + __popcll(bal & lanemask_lt(lane))], g.order[r]);
+                k += total;
+                __syncthreads();
+            }
+            block_sync_agent();
+            for (int ia = 0; ia < k && len == 0; ++ia) {
+                const int a = g_load_i(&g.lnbuf[ia]);
+                const uint64_t *rowa = g.bits + (int64_t)a * g.W;
+                for (int ib = ia + 1; ib < k && len == 0; ++ib) {
+                    const int b = g_load_i(&g.lnbuf[ib]);
+                    if (test_bit(rowa, b)) continue;
+                    len = bfs_path<T>(g, v2, b, a, g.cycle + 1);
+                    if (len > 0) {
+                        if (tid == 0) g.cycle[0] = v2;
+                        len += 1;
+                    }
+                }
+            }
+        }
+    }
+    if (tid == 0) {
+        lexbfs_result_t r;
+        r.chordal = 0;
+        r.witness_v = v;
+        r.witness_p = x;
+        r.witness_z = z;
+        r.cycle_len = len;
+        r.fallback = fb;
+        r.reserved[0] = r.reserved[1] = 0;
+        *g.res = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <int T, bool kGlobal>
+__global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
+{
+    extern __shared__ uint64_t lds[];
+    if (threadIdx.x == 0 && g.failkey) *g.failkey = kNoFail;
+    if (kGlobal) {
+        LdsLayoutG L = carve_lds_g(lds, g.n, T);
+        GlobalTables tab{g.gtab, g.gtab + g.n};
+        BlockTeam<T, true> tm{(int)threadIdx.x};
+        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, tab, L.red);
+    } else {
+        LdsLayout L = carve_lds(lds, g.n, T);
+        BlockTeam<T, false> tm{(int)threadIdx.x};
+        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, L.tab, L.red);
+    }
+}
+
+__global__ __launch_bounds__(kSweepThreads) void k_sweep_single(GDesc g, int rows_per_block, int G, int lg)
+{
+    const int r0 = blockIdx.x * rows_per_block;
+    const int r1 = min(g.n, r0 + rows_per_block);
+    sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, r0, r1, G, lg, g.failkey);
+}
+
+__global__ __launch_bounds__(kFinishThreads) void k_finish_single(GDesc g, uint32_t flags)
+{
+    finish_graph<kFinishThreads>(g, flags);
+}
+
+// Batch: every block first takes large graphs (whole block per graph) from a
+// longest-first queue; once those run out every wave takes small graphs.
+template <int BT>
+__global__ __launch_bounds__(BT) void k_lexbfs_batch(const GDesc *__restrict__ gds, const int32_t *__restrict__ sorted,
+                                                     int nbig, int count, uint32_t *qctr, int wave_region_bytes)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = (int)atomicAdd(&qctr[0], 1u);
+        __syncthreads();
+        const int k = s_idx;
+        __syncthreads();
+        if (k >= nbig) break;
+        const GDesc g = gds[sorted[k]];
+        LdsLayout L = carve_lds(lds, g.n, BT);
+        BlockTeam<BT, false> tm{(int)threadIdx.x};
+        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, L.tab, L.red);
+        __syncthreads();
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    void *region = (char *)lds + (size_t)wave * wave_region_bytes;
+    const int nsmall = count - nbig;
+    for (;;) {
+        int k = 0;
+        if (lane == 0) k = (int)atomicAdd(&qctr[1], 1u);
+        k = __shfl(k, 0, kWave);
+        if (k >= nsmall) break;
+        const GDesc g = gds[sorted[nbig + k]];
+        LdsLayout L = carve_lds(region, g.n, kWave);
+        WaveTeam tm{lane};
+        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, L.tab, L.red);
+        tm.sync();
+    }
+}
+
+__global__ void k_batch_init(const GDesc *__restrict__ gds, int count, uint32_t *qctr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) *gds[i].failkey = kNoFail;
+    if (i == 0) {
+        qctr[0] = 0;
+        qctr[1] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kSweepThreads) void k_sweep_batch(const GDesc *__restrict__ gds,
+                                                               const SweepItem *__restrict__ items)
+{
+    const SweepItem it = items[blockIdx.x];
+    const GDesc &g = gds[it.g];
+    int G = 1, lg = 0;
+    while (G < g.wn && G < kWave) {
+        G <<= 1;
+        ++lg;
+    }
+    sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, it.r0, it.r1, G, lg, g.failkey);
+}
+
+__global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const GDesc *__restrict__ gds, uint32_t flags)
+{
+    const GDesc g = gds[blockIdx.x];
+    finish_graph<kFinishThreads>(g, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct DevInfo {
+    int max_lds = 0;
+    bool attrs_set = false;
+};
+std::mutex g_mu;
+DevInfo g_dev[64];
+
+int device_max_lds()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevInfo &d = g_dev[dev];
+    if (d.max_lds == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return -1;
+        d.max_lds = v;
+    }
+    return d.max_lds;
+}
+
+template <class K>
+bool set_lds_attr(K kernel, size_t bytes)
+{
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+           hipSuccess;
+}
+
+// Team size for one graph on its own: K = ceil(n / T) vertices per lane.
+int single_threads(int n)
+{
+    static int forced = -1;
+    if (forced < 0) {
+        const char *e = getenv("LEXBFS_SINGLE_THREADS");
+        forced = e ? atoi(e) : 0;
+    }
+    int T;
+    if (forced == 64 || forced == 128 || forced == 256 || forced == 512 || forced == 1024) T = forced;
+    else if (n <= 1024) T = 64;
+    else if (n <= 4096) T = 256;
+    else T = 1024;
+    while ((int64_t)T * 64 < n) T <<= 1;
+    return T;
+}
+
+int validate_graph(const lexbfs_graph_t *g)
+{
+    if (!g) return LEXBFS_EINVAL;
+    if (g->n < 0 || g->nnz < 0 || g->nnz >= (int64_t)1 << 31 || g->reserved != 0) return LEXBFS_EINVAL;
+    if (g->n > LEXBFS_MAX_N) return LEXBFS_ETOOBIG;
+    if (g->n == 0) return LEXBFS_OK;
+    if (!g->row_ptr || !g->bits || (g->nnz > 0 && !g->col_idx)) return LEXBFS_EINVAL;
+    if (g->words_per_row < (g->n + 63) / 64) return LEXBFS_EINVAL;
+    return LEXBFS_OK;
+}
+
+// Workspace layout of a single-graph call.
+struct SingleWs {
+    size_t failkey, order, rank, parent, cycle, level, q0, q1, lnbuf, gtab, total;
+};
+
+SingleWs single_layout(int n)
+{
+    SingleWs L;
+    const size_t a = al((size_t)(n > 0 ? n : 1) * 4);
+    size_t off = 0;
+    L.failkey = off; off += kAlign;
+    L.order = off; off += a;
+    L.rank = off; off += a;
+    L.parent = off; off += a;
+    L.cycle = off; off += a;
+    L.level = off; off += a;
+    L.q0 = off; off += a;
+    L.q1 = off; off += a;
+    L.lnbuf = off; off += a;
+    L.gtab = off; off += 2 * a;
+    L.total = off;
+    return L;
+}
+
+template <int T>
+int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
+{
+    const int maxl = device_max_lds();
+    if (maxl <= 0) return LEXBFS_EHIP;
+    const size_t b_lds = lds_bytes_lds_tables(d.n, T);
+    if (b_lds <= (size_t)maxl) {
+        static bool once = false;
+        if (!once) once = set_lds_attr(k_lexbfs_single<T, false>, (size_t)maxl);
+        hipLaunchKernelGGL((k_lexbfs_single<T, false>), dim3(1), dim3(T), b_lds, s, d);
+    } else {
+        const size_t b_g = lds_bytes_global_tables(d.n, T);
+        if (b_g > (size_t)maxl) return LEXBFS_ETOOBIG;
+        static bool once = false;
+        if (!once) once = set_lds_attr(k_lexbfs_single<T, true>, (size_t)maxl);
+        hipLaunchKernelGGL((k_lexbfs_single<T, true>), dim3(1), dim3(T), b_g, s, d);
+    }
+    return hipGetLastError() == hipSuccess ? LEXBFS_OK : LEXBFS_EHIP;
+}
+
+int launch_lexbfs_single(const GDesc &d, hipStream_t s)
+{
+    switch (single_threads(d.n)) {
+        case 64: return launch_lexbfs_single_T<64>(d, s);
+        case 128: return launch_lexbfs_single_T<128>(d, s);
+        case 256: return launch_lexbfs_single_T<256>(d, s);
+        case 512: return launch_lexbfs_single_T<512>(d, s);
+        default: return launch_lexbfs_single_T<1024>(d, s);
+    }
+}
+
+void sweep_shape(int wn, int &G, int &lg)
+{
+    G = 1;
+    lg = 0;
+    while (G < wn && G < kWave) {
+        G <<= 1;
+        ++lg;
+    }
+}
+
+// Rows per sweep block: every group of G lanes takes 4 rows.
+int sweep_rows_per_block(int G) { return (kSweepThreads / kWave) * (kWave / G) * 4; }
+
+GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *order, int32_t *rank,
+                int32_t *parent, int32_t *cycle, lexbfs_result_t *res)
+{
+    GDesc d;
+    d.n = g->n;
+    d.wn = (g->n + 63) / 64;
+    d.W = g->words_per_row;
+    d.rp = g->row_ptr;
+    d.ci = g->col_idx;
+    d.bits = g->bits;
+    d.order = order ? order : (int32_t *)(ws + L.order);
+    d.rank = rank ? rank : (int32_t *)(ws + L.rank);
+    d.parent = parent ? parent : (int32_t *)(ws + L.parent);
+    d.cycle = cycle ? cycle : (int32_t *)(ws + L.cycle);
+    d.level = (int32_t *)(ws + L.level);
+    d.q0 = (int32_t *)(ws + L.q0);
+    d.q1 = (int32_t *)(ws + L.q1);
+    d.lnbuf = (int32_t *)(ws + L.lnbuf);
+    d.failkey = (uint32_t *)(ws + L.failkey);
+    d.gtab = (uint32_t *)(ws + L.gtab);
+    d.res = res;
+    return d;
+}
+
+// Batch plan kept in the workspace.
+struct BatchWs {
+    size_t qctr, gds, sorted, items, failkeys, arrays, total;
+    int nitems;
+};
+
+int batch_items_for(int n, int wn)
+{
+    int G, lg;
+    sweep_shape(wn, G, lg);
+    const int rpb = sweep_rows_per_block(G);
+    return (n + rpb - 1) / rpb;
+}
+
+BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
+{
+    BatchWs L;
+    size_t off = 0;
+    int nitems = 0;
+    size_t arrays = 0;
+    for (int i = 0; i < count; ++i) {
+        const int n = gs[i].n;
+        nitems += n > 0 ? batch_items_for(n, (n + 63) / 64) : 0;
+        arrays += 8 * al((size_t)(n > 0 ? n : 1) * 4);
+    }
+    L.nitems = nitems;
+    L.qctr = off; off += kAlign;
+    L.gds = off; off += al(sizeof(GDesc) * (size_t)count);
+    L.sorted = off; off += al(4 * (size_t)count);
+    L.items = off; off += al(sizeof(SweepItem) * (size_t)(nitems > 0 ? nitems : 1));
+    L.failkeys = off; off += al(4 * (size_t)count);
+    L.arrays = off; off += arrays;
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int lexbfs_abi_version(void) { return kAbiVersion; }
+
+const char *lexbfs_strerror(int code)
+{
+    switch (code) {
+        case LEXBFS_OK: return "ok";
+        case LEXBFS_EINVAL: return "invalid argument";
+        case LEXBFS_ENOWS: return "workspace missing or too small";
+        case LEXBFS_EHIP: return "HIP runtime or launch failure";
+        case LEXBFS_EGRAPH: return "graph violates the input contract";
+        case LEXBFS_ETOOBIG: return "graph too large for this device or library";
+        default: return "unknown error";
+    }
+}
+
+size_t lexbfs_workspace_bytes(int32_t n) { return single_layout(n < 0 ? 0 : n).total; }
+
+int lexbfs_order(const lexbfs_graph_t *g, int32_t *order, int32_t *rank, int32_t *parent, void *ws,
+                 size_t ws_bytes, void *stream)
+{
+    int rc = validate_graph(g);
+    if (rc) return rc;
+    if (!order && g->n > 0) return LEXBFS_EINVAL;
+    const SingleWs L = single_layout(g->n);
+    if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    if (g->n == 0) return LEXBFS_OK;
+    const GDesc d = make_desc(g, (char *)ws, L, order, rank, parent, nullptr, nullptr);
+    return launch_lexbfs_single(d, (hipStream_t)stream);
+}
+
+int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_outputs_t *out, void *ws,
+                 size_t ws_bytes, uint32_t flags, void *stream)
+{
+    int rc = validate_graph(g);
+    if (rc) return rc;
+    if (!res) return LEXBFS_EINVAL;
+    const SingleWs L = single_layout(g->n);
+    if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    hipStream_t s = (hipStream_t)stream;
+    const GDesc d = make_desc(g, (char *)ws, L, out ? out->order : nullptr, out ? out->rank : nullptr,
+                              out ? out->parent : nullptr, out ? out->cycle : nullptr, res);
+    if (g->n > 0) {
+        rc = launch_lexbfs_single(d, s);
+        if (rc) return rc;
+        int G, lg;
+        sweep_shape(d.wn, G, lg);
+        const int rpb = sweep_rows_per_block(G);
+        hipLaunchKernelGGL(k_sweep_single, dim3((d.n + rpb - 1) / rpb), dim3(kSweepThreads), 0, s, d, rpb, G, lg);
+        if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+    }
+    hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), 0, s, d, flags);
+    return hipGetLastError() == hipSuccess ? LEXBFS_OK : LEXBFS_EHIP;
+}
+
+size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
+{
+    if (!gs || count <= 0) return kAlign;
+    return batch_layout(gs, count).total;
+}
+
+int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
+                       lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
+                       uint32_t flags, void *stream)
+{
+    if (count < 0 || (count > 0 && (!gs || !res))) return LEXBFS_EINVAL;
+    if (count == 0) return LEXBFS_OK;
+    constexpr int BT = 256;
+    int wave_max_n = 1024;
+    if (tuning) {
+        if (tuning->block_threads != 0 && tuning->block_threads != BT) return LEXBFS_EINVAL;
+        if (tuning->wave_max_n > 0) wave_max_n = tuning->wave_max_n;
+    }
+    wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
+    int maxn_block = 0, maxn_wave = 0;
+    for (int i = 0; i < count; ++i) {
+        const int rc = validate_graph(&gs[i]);
+        if (rc) return rc;
+        if (gs[i].n > wave_max_n) maxn_block = std::max(maxn_block, gs[i].n);
+        else maxn_wave = std::max(maxn_wave, gs[i].n);
+    }
+    if (maxn_block > 64 * BT) return LEXBFS_ETOOBIG;
+    const int maxl = device_max_lds();
+    if (maxl <= 0) return LEXBFS_EHIP;
+    const size_t region = maxn_wave > 0 ? lds_bytes_lds_tables(maxn_wave, kWave) : 0;
+    size_t lds = std::max(lds_bytes_lds_tables(std::max(maxn_block, 1), BT), region * (BT / kWave));
+    if (tuning && tuning->lds_bytes > 0) lds = std::max(lds, (size_t)tuning->lds_bytes);
+    if (lds > (size_t)maxl) return LEXBFS_ETOOBIG;
+
+    const BatchWs L = batch_layout(gs, count);
+    if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    char *w = (char *)ws;
+
+    // Host plan: descriptors, longest-first order, sweep items.
+    std::vector<char> plan(L.failkeys - L.gds);
+    GDesc *hd = (GDesc *)plan.data();
+    int32_t *hsorted = (int32_t *)(plan.data() + (L.sorted - L.gds));
+    SweepItem *hitems = (SweepItem *)(plan.data() + (L.items - L.gds));
+    size_t aoff = L.arrays;
+    for (int i = 0; i < count; ++i) {
+        const lexbfs_graph_t &g = gs[i];
+        const size_t a = al((size_t)(g.n > 0 ? g.n : 1) * 4);
+        GDesc &d = hd[i];
+        d.n = g.n;
+        d.wn = (g.n + 63) / 64;
+        d.W = g.words_per_row;
+        d.rp = g.row_ptr;
+        d.ci = g.col_idx;
+        d.bits = g.bits;
+        const lexbfs_outputs_t *o = outs ? &outs[i] : nullptr;
+        d.order = (o && o->order) ? o->order : (int32_t *)(w + aoff);
+        aoff += a;
+        d.rank = (o && o->rank) ? o->rank : (int32_t *)(w + aoff);
+        aoff += a;
+        d.parent = (o && o->parent) ? o->parent : (int32_t *)(w + aoff);
+        aoff += a;
+        d.cycle = (o && o->cycle) ? o->cycle : (int32_t *)(w + aoff);
+        aoff += a;
+        d.level = (int32_t *)(w + aoff);
+        aoff += a;
+        d.q0 = (int32_t *)(w + aoff);
+        aoff += a;
+        d.q1 = (int32_t *)(w + aoff);
+        aoff += a;
+        d.lnbuf = (int32_t *)(w + aoff);
+        aoff += a;
+        d.failkey = (uint32_t *)(w + L.failkeys) + i;
+        d.gtab = nullptr;
+        d.res = res + i;
+        hsorted[i] = i;
+    }
+    std::stable_sort(hsorted, hsorted + count, [&](int a, int b) { return gs[a].n > gs[b].n; });
+    int nbig = 0;
+    while (nbig < count && gs[hsorted[nbig]].n > wave_max_n) ++nbig;
+    int it = 0;
+    for (int k = 0; k < count; ++k) {  // sweep items, largest graphs first
+        const int i = hsorted[k];
+        const int n = gs[i].n;
+        if (n <= 0) continue;
+        int G, lg;
+        sweep_shape((n + 63) / 64, G, lg);
+        const int rpb = sweep_rows_per_block(G);
+        for (int r0 = 0; r0 < n; r0 += rpb) hitems[it++] = SweepItem{i, r0, std::min(n, r0 + rpb), 0};
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(w + L.gds, plan.data(), plan.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return LEXBFS_EHIP;
+    const GDesc *dg = (const GDesc *)(w + L.gds);
+    uint32_t *qctr = (uint32_t *)(w + L.qctr);
+    hipLaunchKernelGGL(k_batch_init, dim3((count + 255) / 256), dim3(256), 0, s, dg, count, qctr);
+    if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+    {
+        static bool once = false;
+        if (!once) once = set_lds_attr(k_lexbfs_batch<BT>, (size_t)maxl);
+        int cus = 256;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+        const int per_cu = std::max(1, (int)(maxl / lds));
+        const int blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
+        hipLaunchKernelGGL((k_lexbfs_batch<BT>), dim3(blocks), dim3(BT), lds, s, dg,
+                           (const int32_t *)(w + L.sorted), nbig, count, qctr, (int)region);
+        if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+    }
+    if (it > 0) {
+        hipLaunchKernelGGL(k_sweep_batch, dim3(it), dim3(kSweepThreads), 0, s, dg, (const SweepItem *)(w + L.items));
+        if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+    }
+    hipLaunchKernelGGL(k_finish_batch, dim3(count), dim3(kFinishThreads), 0, s, dg, flags);
+    return hipGetLastError() == hipSuccess ? LEXBFS_OK : LEXBFS_EHIP;
+}
+
+}  // extern "C"

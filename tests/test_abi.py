@@ -1,0 +1,122 @@
+"""The C ABI library without a GPU: it loads, exports every symbol the
+header declares, its structs match the Python binding, and argument errors
+come back as the documented codes before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1508_06329_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lexbfs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("liblexbfs.so not built")
+    return _lib.load()
+
+
+def test_header_declares_the_binding_list():
+    assert declared_functions() == sorted(_lib.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    for name in declared_functions():
+        assert re.search(rf"\bT {name}$", out, flags=re.M), name
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lexbfs.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lexbfs_graph_t), '
+                   'offsetof(lexbfs_graph_t, nnz), offsetof(lexbfs_graph_t, bits), offsetof(lexbfs_graph_t, words_per_row), '
+                   'sizeof(lexbfs_result_t), sizeof(lexbfs_outputs_t), sizeof(lexbfs_tuning_t)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    exp = [ctypes.sizeof(_lib.lexbfs_graph_t), _lib.lexbfs_graph_t.nnz.offset, _lib.lexbfs_graph_t.bits.offset,
+           _lib.lexbfs_graph_t.words_per_row.offset, ctypes.sizeof(_lib.lexbfs_result_t),
+           ctypes.sizeof(_lib.lexbfs_outputs_t), ctypes.sizeof(_lib.lexbfs_tuning_t)]
+    assert got == exp
+    assert got[4] == 32
+
+
+def fake_graph(n, W=None, nnz=10):
+    g = _lib.lexbfs_graph_t()
+    g.n = n
+    g.reserved = 0
+    g.nnz = nnz
+    # non-null placeholders: argument checks never dereference them
+    g.row_ptr = 0x1000
+    g.col_idx = 0x2000
+    g.bits = 0x3000
+    g.words_per_row = (n + 63) // 64 if W is None else W
+    return g
+
+
+def test_argument_errors(lib):
+    ws_need = lib.lexbfs_workspace_bytes(100)
+    ws = 0x10000
+    res = 0x20000
+    order = 0x30000
+    assert lib.lexbfs_order(None, order, None, None, ws, ws_need, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(-1)
+    assert lib.lexbfs_order(ctypes.byref(g), order, None, None, ws, ws_need, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(_lib.LEXBFS_MAX_N + 1)
+    assert lib.lexbfs_order(ctypes.byref(g), order, None, None, ws, 1 << 40, None) == _lib.LEXBFS_ETOOBIG
+    g = fake_graph(100, W=1)
+    assert lib.lexbfs_order(ctypes.byref(g), order, None, None, ws, ws_need, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(100)
+    assert lib.lexbfs_order(ctypes.byref(g), order, None, None, ws, ws_need - 1, None) == _lib.LEXBFS_ENOWS
+    assert lib.lexbfs_order(ctypes.byref(g), order, None, None, None, ws_need, None) == _lib.LEXBFS_ENOWS
+    assert lib.lexbfs_order(ctypes.byref(g), None, None, None, ws, ws_need, None) == _lib.LEXBFS_EINVAL
+    g.reserved = 1
+    assert lib.chordal_test(ctypes.byref(g), res, None, ws, ws_need, 0, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(100)
+    g.nnz = 1 << 31
+    assert lib.chordal_test(ctypes.byref(g), res, None, ws, ws_need, 0, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(100)
+    g.bits = None
+    assert lib.chordal_test(ctypes.byref(g), res, None, ws, ws_need, 0, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(100)
+    assert lib.chordal_test(ctypes.byref(g), None, None, ws, ws_need, 0, None) == _lib.LEXBFS_EINVAL
+    assert lib.chordal_test(ctypes.byref(g), res, None, ws, 16, 0, None) == _lib.LEXBFS_ENOWS
+    # batch
+    arr = (_lib.lexbfs_graph_t * 2)(fake_graph(10), fake_graph(-3))
+    assert lib.chordal_test_batch(arr, 2, None, res, None, ws, 1 << 30, 0, None) == _lib.LEXBFS_EINVAL
+    assert lib.chordal_test_batch(arr, -1, None, res, None, ws, 1 << 30, 0, None) == _lib.LEXBFS_EINVAL
+    assert lib.chordal_test_batch(arr, 0, None, res, None, ws, 0, 0, None) == _lib.LEXBFS_OK
+    arr = (_lib.lexbfs_graph_t * 2)(fake_graph(10), fake_graph(70000))
+    assert lib.chordal_test_batch(arr, 2, None, res, None, ws, 1 << 30, 0, None) == _lib.LEXBFS_ETOOBIG
+    tun = _lib.lexbfs_tuning_t(0, 999, 0, 0)
+    arr = (_lib.lexbfs_graph_t * 1)(fake_graph(10))
+    assert lib.chordal_test_batch(arr, 1, None, res, ctypes.byref(tun), ws, 1 << 30, 0, None) == _lib.LEXBFS_EINVAL
+    small = lib.lexbfs_batch_workspace_bytes(arr, 1)
+    assert lib.chordal_test_batch(arr, 1, None, res, None, ws, 0, 0, None) in (_lib.LEXBFS_ENOWS, _lib.LEXBFS_EHIP)
+    assert small > 0
+
+
+def test_workspace_sizes_grow(lib):
+    sizes = [lib.lexbfs_workspace_bytes(n) for n in (0, 1, 64, 1000, 65536)]
+    assert sizes == sorted(sizes) and sizes[0] > 0
+    assert lib.lexbfs_workspace_bytes(65536) >= 10 * 4 * 65536
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert lib.lexbfs_strerror(code)
+    assert lib.lexbfs_abi_version() >= 1

@@ -1,0 +1,196 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle,
+element by element (orders, ranks, parents, verdicts, witnesses and
+certificates are integers: the bar is bit-exact)."""
+import itertools
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1508_06329_amd as lx  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def check_single(g, flags=0, tag=""):
+    say(f"[parity] {tag} {g.name} n={g.n} m={g.m} flags={flags}")
+    ref = oracle.chordal_test(g)
+    dg = lx.DeviceGraph.from_host(g, DEV)
+    r = lx.chordal_test(dg, flags=flags)
+    assert np.array_equal(r.order.cpu().numpy(), ref.order), "order"
+    assert np.array_equal(r.rank.cpu().numpy(), ref.rank), "rank"
+    assert np.array_equal(r.parent.cpu().numpy(), ref.parent), "parent"
+    assert r.chordal == ref.chordal
+    if flags & lx.LEXBFS_FLAG_FORCE_FALLBACK and not ref.chordal:
+        cyc, fb = oracle.certificate(g, ref.order, ref.rank, ref.witness, force_fallback=True)
+        assert r.fallback and fb
+        assert r.witness == ref.witness
+        assert r.cycle_list == cyc.tolist()
+    else:
+        assert r.witness == ref.witness
+        assert r.cycle_list == ref.cycle.tolist()
+        assert r.fallback == ref.fallback
+    return r, ref
+
+
+# ---------------------------------------------------------------------------
+# Small and structured graphs
+# ---------------------------------------------------------------------------
+
+def structured_cases():
+    cases = []
+    for n in (0, 1, 2, 3, 5, 63, 64, 65, 127, 129, 1000):
+        cases.append(gg.from_edges(n, list(itertools.combinations(range(n), 2)) if n <= 300 else [], f"K{n}"))
+        cases.append(gg.from_edges(n, [], f"E{n}"))
+        cases.append(gg.from_edges(n, [(i, i + 1) for i in range(n - 1)], f"P{n}"))
+        if n >= 4:
+            cases.append(gg.from_edges(n, [(i, (i + 1) % n) for i in range(n)], f"C{n}"))
+        if n >= 3:
+            cases.append(gg.from_edges(n, [(n // 2, v) for v in range(n) if v != n // 2], f"S{n}"))
+    from conftest import load_golden
+    for name in ("c4.txt", "c5.txt", "two_triangles.txt"):
+        ex = load_golden(name)
+        cases.append(gg.from_edges(ex["n"], ex["edges"], name))
+    return cases
+
+
+@pytest.mark.parametrize("idx", range(len(structured_cases())))
+def test_structured(idx):
+    g = structured_cases()[idx]
+    check_single(g, tag=f"structured[{idx}]")
+
+
+@pytest.mark.parametrize("n,p,seed", [(10, 0.4, 1), (50, 0.2, 2), (64, 0.5, 3), (100, 0.05, 4), (300, 0.02, 5),
+                                      (700, 0.3, 6), (1500, 0.004, 7), (4097, 0.002, 8), (5000, 0.3, 9),
+                                      (9000, 0.001, 10)])
+def test_random_gnp(n, p, seed):
+    check_single(gg.gnp(n, p, seed), tag="gnp")
+
+
+@pytest.mark.parametrize("n,T,s,seed", [(100, 30, 5, 1), (1024, 256, 8, 2), (3000, 700, 10, 3), (8000, 2000, 12, 4)])
+def test_random_subtree(n, T, s, seed):
+    g = gg.subtree(n, T, s, seed)
+    check_single(g, tag="subtree")
+    h = gg.plant(g, 4 + seed, seed + 100)
+    check_single(h, tag="planted")
+
+
+@pytest.mark.parametrize("K,I,a", [(20, 100, 5), (200, 2000, 16)])
+def test_split_pairs(K, I, a):
+    for g in gg.split_pair(K, I, a, 7):
+        check_single(g, tag="split")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_forced_fallback(seed):
+    g = gg.gnp(200, 0.03, 50 + seed)
+    check_single(g, flags=lx.LEXBFS_FLAG_FORCE_FALLBACK, tag="fallback")
+    h = gg.plant(gg.subtree(300, 80, 6, seed), 6, seed)
+    check_single(h, flags=lx.LEXBFS_FLAG_FORCE_FALLBACK, tag="fallback")
+
+
+# ---------------------------------------------------------------------------
+# Full-size single-graph workloads
+# ---------------------------------------------------------------------------
+
+def test_workload_small_full():
+    for g in gg.config_single_small():
+        check_single(g, tag="N=1024 workload")
+
+
+def test_workload_large_sparse_full():
+    for g in gg.config_single_large():
+        check_single(g, tag="N=16384 workload")
+
+
+def test_workload_split_65536_full():
+    for g in gg.config_worst_steps():
+        r, ref = check_single(g, tag="N=65536 split workload")
+    assert not ref.chordal and len(ref.cycle) == 4
+
+
+# ---------------------------------------------------------------------------
+# lexbfs_order entry point, determinism
+# ---------------------------------------------------------------------------
+
+def test_lexbfs_order_entry_point():
+    g = gg.subtree(2000, 500, 8, 11)
+    ref = oracle.lexbfs(g)
+    dg = lx.DeviceGraph.from_host(g, DEV)
+    order, rank, parent = lx.lexbfs_order(dg)
+    torch.cuda.synchronize()
+    assert np.array_equal(order.cpu().numpy(), ref.order)
+    assert np.array_equal(rank.cpu().numpy(), ref.rank)
+    assert np.array_equal(parent.cpu().numpy(), ref.parent)
+
+
+def test_repeat_is_deterministic():
+    g = gg.gnp(3000, 0.01, 99)
+    dg = lx.DeviceGraph.from_host(g, DEV)
+    a = lx.chordal_test(dg)
+    b = lx.chordal_test(dg, stream=torch.cuda.Stream())
+    assert torch.equal(a.order, b.order) and a.witness == b.witness and a.cycle_list == b.cycle_list
+
+
+# ---------------------------------------------------------------------------
+# Batch
+# ---------------------------------------------------------------------------
+
+def check_batch(graphs, tuning=None, tag=""):
+    say(f"[parity] batch {tag} count={len(graphs)} tuning={tuning}")
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.chordal_test_batch(dgs, outputs=True, tuning=tuning)
+    for g, r in zip(graphs, rs):
+        ref = oracle.chordal_test(g)
+        assert np.array_equal(r.order.cpu().numpy(), ref.order), g.name
+        assert np.array_equal(r.parent.cpu().numpy(), ref.parent), g.name
+        assert r.chordal == ref.chordal and r.witness == ref.witness, g.name
+        assert r.cycle_list == ref.cycle.tolist(), g.name
+    return rs
+
+
+def test_batch_mix_small():
+    graphs = gg.config_batch(count=96, lo=32, hi=4096, seed=5)
+    graphs += [gg.from_edges(0, []), gg.from_edges(1, []), gg.from_edges(5, [(i, (i + 1) % 5) for i in range(5)])]
+    check_batch(graphs, tag="mix")
+    check_batch(graphs, tuning={"wave_max_n": 256}, tag="mix")
+    check_batch(graphs, tuning={"wave_max_n": 4096}, tag="mix")
+
+
+def test_batch_equals_single():
+    graphs = gg.config_batch(count=24, lo=32, hi=2000, seed=6)
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.chordal_test_batch(dgs, outputs=True)
+    for dg, r in zip(dgs, rs):
+        s = lx.chordal_test(dg)
+        assert torch.equal(s.order, r.order) and s.witness == r.witness and s.cycle_list == r.cycle_list
+
+
+def test_batch_workload_full():
+    graphs = gg.config_batch()  # 4,096 graphs, N log-uniform on [32, 4096]
+    say(f"[parity] batch workload full count={len(graphs)}")
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.chordal_test_batch(dgs, outputs=True)
+    bad = []
+    for i, (g, r) in enumerate(zip(graphs, rs)):
+        ref = oracle.chordal_test(g)
+        if not (np.array_equal(r.order.cpu().numpy(), ref.order) and r.chordal == ref.chordal
+                and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()):
+            bad.append(i)
+    assert bad == []
+    assert sum(r.chordal for r in rs) == 2048
