@@ -168,6 +168,11 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
 /* Short English description of a return code (static storage). */
 const char *lexbfs_strerror(int code);
 
+/* Description of the most recent failure on the calling thread: the HIP
+ * call and its error string after LEXBFS_EHIP, or the limit that was hit
+ * after LEXBFS_ETOOBIG (static thread-local storage, "" if none). */
+const char *lexbfs_last_error(void);
+
 /* Library ABI version (incremented on incompatible changes). */
 int lexbfs_abi_version(void);
 

@@ -26,7 +26,7 @@ LEXBFS_MAX_N = 65536
 LEXBFS_FLAG_FORCE_FALLBACK = 0x1
 
 EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_order", "chordal_test", "lexbfs_batch_workspace_bytes",
-            "chordal_test_batch", "lexbfs_strerror", "lexbfs_abi_version"]
+            "chordal_test_batch", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_abi_version"]
 
 
 class lexbfs_graph_t(ctypes.Structure):
@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(lexbfs_tuning_t), vp, sz, ctypes.c_uint32, vp]
     lib.lexbfs_strerror.restype = ctypes.c_char_p
     lib.lexbfs_strerror.argtypes = [ctypes.c_int]
+    lib.lexbfs_last_error.restype = ctypes.c_char_p
+    lib.lexbfs_last_error.argtypes = []
     lib.lexbfs_abi_version.restype = ctypes.c_int
     lib.lexbfs_abi_version.argtypes = []
     _lib = lib
@@ -99,7 +101,11 @@ def load() -> ctypes.CDLL:
 
 class LexbfsError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
-        msg = load().lexbfs_strerror(code).decode()
+        lib = load()
+        msg = lib.lexbfs_strerror(code).decode()
+        detail = lib.lexbfs_last_error().decode()
+        if detail:
+            msg = f"{msg} [{detail}]"
         super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
         self.code = code
 

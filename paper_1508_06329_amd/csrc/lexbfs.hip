@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -24,6 +25,27 @@ constexpr int kAbiVersion = 1;
 constexpr size_t kAlign = 256;
 constexpr int kSweepThreads = 256;
 constexpr int kFinishThreads = 256;
+
+// Description of the last failure on this thread (lexbfs_last_error).
+thread_local char t_last_error[256] = "";
+
+int fail_hip(hipError_t e, const char *where)
+{
+    snprintf(t_last_error, sizeof t_last_error, "%s: %s", where, hipGetErrorString(e));
+    return LEXBFS_EHIP;
+}
+
+int fail_code(int code, const char *what)
+{
+    snprintf(t_last_error, sizeof t_last_error, "%s", what);
+    return code;
+}
+
+#define LX_CHECK_LAUNCH(where)                                  \
+    do {                                                        \
+        const hipError_t e_ = hipGetLastError();                \
+        if (e_ != hipSuccess) return fail_hip(e_, where);       \
+    } while (0)
 
 // Everything a kernel needs about one graph (device copy for batches).
 struct GDesc {
@@ -398,11 +420,29 @@ int device_max_lds()
     return d.max_lds;
 }
 
+// Largest dynamic LDS a kernel may request: the device limit minus the
+// kernel's static LDS. Raises the kernel's dynamic-LDS cap to that value
+// once. Returns 0 on failure.
 template <class K>
-bool set_lds_attr(K kernel, size_t bytes)
+size_t dynamic_lds_limit(K kernel)
 {
-    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-           hipSuccess;
+    static size_t limit = 0;  // one cache per kernel instantiation
+    if (limit) return limit;
+    const int maxl = device_max_lds();
+    if (maxl <= 0) return 0;
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, (const void *)kernel) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const size_t lim = (size_t)maxl - fa.sharedSizeBytes;
+    if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    limit = lim;
+    return limit;
 }
 
 // Team size for one graph on its own: K = ceil(n / T) vertices per lane.
@@ -460,21 +500,19 @@ SingleWs single_layout(int n)
 template <int T>
 int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
 {
-    const int maxl = device_max_lds();
-    if (maxl <= 0) return LEXBFS_EHIP;
+    const size_t lim_lds = dynamic_lds_limit(k_lexbfs_single<T, false>);
+    const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, true>);
+    if (!lim_lds || !lim_g) return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
     const size_t b_lds = lds_bytes_lds_tables(d.n, T);
-    if (b_lds <= (size_t)maxl) {
-        static bool once = false;
-        if (!once) once = set_lds_attr(k_lexbfs_single<T, false>, (size_t)maxl);
+    if (b_lds <= lim_lds) {
         hipLaunchKernelGGL((k_lexbfs_single<T, false>), dim3(1), dim3(T), b_lds, s, d);
     } else {
         const size_t b_g = lds_bytes_global_tables(d.n, T);
-        if (b_g > (size_t)maxl) return LEXBFS_ETOOBIG;
-        static bool once = false;
-        if (!once) once = set_lds_attr(k_lexbfs_single<T, true>, (size_t)maxl);
+        if (b_g > lim_g) return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
         hipLaunchKernelGGL((k_lexbfs_single<T, true>), dim3(1), dim3(T), b_g, s, d);
     }
-    return hipGetLastError() == hipSuccess ? LEXBFS_OK : LEXBFS_EHIP;
+    LX_CHECK_LAUNCH("LexBFS launch");
+    return LEXBFS_OK;
 }
 
 int launch_lexbfs_single(const GDesc &d, hipStream_t s)
@@ -570,6 +608,8 @@ extern "C" {
 
 int lexbfs_abi_version(void) { return kAbiVersion; }
 
+const char *lexbfs_last_error(void) { return t_last_error; }
+
 const char *lexbfs_strerror(int code)
 {
     switch (code) {
@@ -616,10 +656,11 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
         sweep_shape(d.wn, G, lg);
         const int rpb = sweep_rows_per_block(G);
         hipLaunchKernelGGL(k_sweep_single, dim3((d.n + rpb - 1) / rpb), dim3(kSweepThreads), 0, s, d, rpb, G, lg);
-        if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+        LX_CHECK_LAUNCH("sweep launch");
     }
     hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), 0, s, d, flags);
-    return hipGetLastError() == hipSuccess ? LEXBFS_OK : LEXBFS_EHIP;
+    LX_CHECK_LAUNCH("certificate launch");
+    return LEXBFS_OK;
 }
 
 size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
@@ -648,16 +689,15 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
         if (gs[i].n > wave_max_n) maxn_block = std::max(maxn_block, gs[i].n);
         else maxn_wave = std::max(maxn_wave, gs[i].n);
     }
-    if (maxn_block > 64 * BT) return LEXBFS_ETOOBIG;
-    const int maxl = device_max_lds();
-    if (maxl <= 0) return LEXBFS_EHIP;
+    if (maxn_block > 64 * BT) return fail_code(LEXBFS_ETOOBIG, "a batch graph exceeds 64 vertices per lane");
+    const BatchWs L = batch_layout(gs, count);
+    if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    const size_t maxl = dynamic_lds_limit(k_lexbfs_batch<BT>);
+    if (!maxl) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
     const size_t region = maxn_wave > 0 ? lds_bytes_lds_tables(maxn_wave, kWave) : 0;
     size_t lds = std::max(lds_bytes_lds_tables(std::max(maxn_block, 1), BT), region * (BT / kWave));
     if (tuning && tuning->lds_bytes > 0) lds = std::max(lds, (size_t)tuning->lds_bytes);
-    if (lds > (size_t)maxl) return LEXBFS_ETOOBIG;
-
-    const BatchWs L = batch_layout(gs, count);
-    if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    if (lds > maxl) return fail_code(LEXBFS_ETOOBIG, "batch graph state does not fit the workgroup LDS");
     char *w = (char *)ws;
 
     // Host plan: descriptors, longest-first order, sweep items.
@@ -712,30 +752,31 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
         for (int r0 = 0; r0 < n; r0 += rpb) hitems[it++] = SweepItem{i, r0, std::min(n, r0 + rpb), 0};
     }
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(w + L.gds, plan.data(), plan.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-        return LEXBFS_EHIP;
+    {
+        const hipError_t e = hipMemcpyAsync(w + L.gds, plan.data(), plan.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return fail_hip(e, "staging the batch plan");
+    }
     const GDesc *dg = (const GDesc *)(w + L.gds);
     uint32_t *qctr = (uint32_t *)(w + L.qctr);
     hipLaunchKernelGGL(k_batch_init, dim3((count + 255) / 256), dim3(256), 0, s, dg, count, qctr);
-    if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+    LX_CHECK_LAUNCH("batch init launch");
     {
-        static bool once = false;
-        if (!once) once = set_lds_attr(k_lexbfs_batch<BT>, (size_t)maxl);
         int cus = 256;
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-        const int per_cu = std::max(1, (int)(maxl / lds));
+        const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
         const int blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
         hipLaunchKernelGGL((k_lexbfs_batch<BT>), dim3(blocks), dim3(BT), lds, s, dg,
                            (const int32_t *)(w + L.sorted), nbig, count, qctr, (int)region);
-        if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+        LX_CHECK_LAUNCH("batch LexBFS launch");
     }
     if (it > 0) {
         hipLaunchKernelGGL(k_sweep_batch, dim3(it), dim3(kSweepThreads), 0, s, dg, (const SweepItem *)(w + L.items));
-        if (hipGetLastError() != hipSuccess) return LEXBFS_EHIP;
+        LX_CHECK_LAUNCH("batch sweep launch");
     }
     hipLaunchKernelGGL(k_finish_batch, dim3(count), dim3(kFinishThreads), 0, s, dg, flags);
-    return hipGetLastError() == hipSuccess ? LEXBFS_OK : LEXBFS_EHIP;
+    LX_CHECK_LAUNCH("batch certificate launch");
+    return LEXBFS_OK;
 }
 
 }  // extern "C"
