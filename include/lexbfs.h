@@ -155,15 +155,36 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count);
  *   outs    HOST array [count] of optional outputs, or NULL
  *   res     DEVICE array [count] of results
  *   tuning  HOST pointer or NULL for the built-in schedule
- * The per-graph descriptor table is staged into the workspace with a
- * host-to-device copy on `stream`; the calling thread returns once the
- * table has been staged. Every graph needs n <= LEXBFS_MAX_N and must fit
+ * Equivalent to lexbfs_batch_plan_create + lexbfs_batch_plan_launch +
+ * lexbfs_batch_plan_destroy: the per-graph descriptor table is staged into
+ * the workspace with a host-to-device copy on `stream`; the calling thread
+ * returns once the table has been staged. Every graph needs n <= LEXBFS_MAX_N and must fit
  * the workgroup's LDS (n <= 16384 with the built-in schedule).
  * Errors: as chordal_test; LEXBFS_ETOOBIG names a graph beyond the limit.
  */
 int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
                        lexbfs_result_t *res, const lexbfs_tuning_t *tuning,
                        void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * Prepared batches. lexbfs_batch_plan_create validates the graphs, fixes the
+ * schedule (longest-first queue, team per graph, sweep work items) and stages
+ * the descriptor table into `ws` with a host-to-device copy on `stream`
+ * (the call returns once the table has been staged). lexbfs_batch_plan_launch
+ * then only launches kernels on `stream`, so it may be called many times
+ * (the graphs' contents may change between launches, their sizes and
+ * addresses may not) and may be captured into a hipGraph. Results of a
+ * launch are valid once the stream reaches it. The plan is host memory owned
+ * by the caller until lexbfs_batch_plan_destroy; the workspace must stay
+ * allocated while the plan is used and must not be shared by two plans whose
+ * launches overlap. Arguments and errors as chordal_test_batch.
+ */
+typedef struct lexbfs_batch_plan lexbfs_batch_plan_t;
+int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
+                             lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
+                             uint32_t flags, void *stream, lexbfs_batch_plan_t **plan);
+int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *plan, void *stream);
+void lexbfs_batch_plan_destroy(lexbfs_batch_plan_t *plan);
 
 /* Short English description of a return code (static storage). */
 const char *lexbfs_strerror(int code);
@@ -172,6 +193,18 @@ const char *lexbfs_strerror(int code);
  * call and its error string after LEXBFS_EHIP, or the limit that was hit
  * after LEXBFS_ETOOBIG (static thread-local storage, "" if none). */
 const char *lexbfs_last_error(void);
+
+/* Kernel timing (a tracing aid). While enabled, every kernel launch of the
+ * library is bracketed by a pair of HIP events recorded on the launch's
+ * stream; the events are created by the enabling call, never on the launch
+ * path. lexbfs_profile_collect waits for the recorded events, writes per
+ * kernel kind (index below) the number of launches and their summed
+ * duration in milliseconds since the previous collect, and returns the
+ * number of launches that found the event pool (8192 pairs) full, or < 0 on
+ * a HIP failure. counts/ms: host arrays of LEXBFS_KERNEL_KINDS entries. */
+#define LEXBFS_KERNEL_KINDS 4 /* 0 LexBFS, 1 elimination sweep, 2 witness and certificate, 3 batch setup */
+int lexbfs_profile_enable(int on);
+int lexbfs_profile_collect(int32_t *counts, double *ms);
 
 /* Library ABI version (incremented on incompatible changes). */
 int lexbfs_abi_version(void);

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_MAX_N, LexbfsError, lexbfs_graph_t, lexbfs_outputs_t,
                    lexbfs_result_t, lexbfs_tuning_t)
 
-__all__ = ["DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
+__all__ = ["BatchPlan", "pack_graphs", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
            "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK"]
 
 
@@ -82,6 +82,33 @@ class Result:
         if self.cycle is None or self.cycle_len == 0:
             return []
         return self.cycle[: self.cycle_len].tolist()
+
+
+class KernelTimer:
+    """HIP-event timing of every library kernel launch while active.
+
+    with KernelTimer() as kt: ...; kt.result() -> {kind: (launches, total_ms)}
+    """
+
+    def __enter__(self):
+        _lib.check(_lib.load().lexbfs_profile_enable(1), "lexbfs_profile_enable")
+        self.collect()  # discard anything older
+        return self
+
+    def collect(self):
+        lib = _lib.load()
+        counts = (ctypes.c_int32 * _lib.LEXBFS_KERNEL_KINDS)()
+        ms = (ctypes.c_double * _lib.LEXBFS_KERNEL_KINDS)()
+        rc = lib.lexbfs_profile_collect(counts, ms)
+        if rc < 0:
+            _lib.check(rc, "lexbfs_profile_collect")
+        self.dropped = rc
+        self.last = {name: (int(counts[i]), float(ms[i])) for i, name in enumerate(_lib.KERNEL_KIND_NAMES)}
+        return self.last
+
+    def __exit__(self, *exc):
+        _lib.load().lexbfs_profile_enable(0)
+        return False
 
 
 def workspace_bytes(n: int) -> int:
@@ -198,3 +225,97 @@ def chordal_test_batch(graphs: Sequence[DeviceGraph], flags: int = 0, stream=Non
         kw = {k: v[: g.n] for k, v in tens[i].items()} if outputs else {}
         out.append(Result(chordal, wit, clen, fb, **kw))
     return out
+
+
+def pack_graphs(graphs, device="cuda") -> List[DeviceGraph]:
+    """Upload many host graphs with three copies: one pool each for row
+    pointers, column indices and bitsets; every DeviceGraph is a view into
+    the pools. Bitsets start on 16-byte boundaries."""
+    import numpy as np
+
+    rp_off, ci_off, b_off = [0], [0], [0]
+    for g in graphs:
+        rp_off.append(rp_off[-1] + g.n + 1)
+        ci_off.append(ci_off[-1] + max(g.nnz, 0))
+        nb = max(g.n * g.W, 1)
+        b_off.append(b_off[-1] + nb + (nb & 1))
+    rp = np.empty(rp_off[-1], dtype=np.int32)
+    ci = np.empty(max(ci_off[-1], 1), dtype=np.int32)
+    bits = np.zeros(max(b_off[-1], 1), dtype=np.uint64)
+    for i, g in enumerate(graphs):
+        rp[rp_off[i]:rp_off[i + 1]] = g.row_ptr
+        ci[ci_off[i]:ci_off[i + 1]] = g.col_idx[: g.nnz]
+        nb = g.n * g.W
+        bits[b_off[i]:b_off[i] + nb] = g.bits[:nb]
+    t_rp = torch.from_numpy(rp).to(device)
+    t_ci = torch.from_numpy(ci).to(device)
+    t_b = torch.from_numpy(bits.view(np.int64)).to(device)
+    out = []
+    for i, g in enumerate(graphs):
+        out.append(DeviceGraph(g.n, g.W, t_rp[rp_off[i]:rp_off[i + 1]], t_ci[ci_off[i]:ci_off[i] + g.nnz],
+                               t_b[b_off[i]:b_off[i] + max(g.n * g.W, 1)]))
+    return out
+
+
+class BatchPlan:
+    """A prepared batch (lexbfs_batch_plan_*): the schedule and descriptor
+    table are built once; launch() only launches the kernels, so it is cheap
+    to repeat and may be captured into a HIP graph."""
+
+    def __init__(self, graphs: Sequence[DeviceGraph], outputs: bool = False, tuning: Optional[dict] = None,
+                 flags: int = 0, stream=None):
+        lib = _lib.load()
+        self.graphs = list(graphs)
+        count = len(self.graphs)
+        dev = self.graphs[0].device if count else torch.device("cuda")
+        self.arr = (lexbfs_graph_t * max(count, 1))(*[g.desc() for g in self.graphs])
+        self.tens = []
+        self.outs_arr = None
+        if outputs and count:
+            self.outs_arr = (lexbfs_outputs_t * count)()
+            for i, g in enumerate(self.graphs):
+                t = {k: torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+                     for k in ("order", "rank", "parent", "cycle")}
+                self.tens.append(t)
+                for k, v in t.items():
+                    setattr(self.outs_arr[i], k, v.data_ptr())
+        self.res = torch.zeros((max(count, 1), 8), dtype=torch.int32, device=dev)
+        need = int(lib.lexbfs_batch_workspace_bytes(self.arr, count))
+        self.ws = _workspace(need, dev)
+        tun = None
+        if tuning:
+            t = lexbfs_tuning_t()
+            t.wave_max_n = int(tuning.get("wave_max_n", 0))
+            t.block_threads = int(tuning.get("block_threads", 0))
+            t.lds_bytes = int(tuning.get("lds_bytes", 0))
+            self._tun = t
+            tun = ctypes.byref(t)
+        self.handle = ctypes.c_void_p()
+        rc = lib.lexbfs_batch_plan_create(self.arr, count, self.outs_arr, self.res.data_ptr(), tun,
+                                          self.ws.data_ptr(), self.ws.numel(), flags, _stream_handle(stream),
+                                          ctypes.byref(self.handle))
+        _lib.check(rc, "lexbfs_batch_plan_create")
+
+    def launch(self, stream=None):
+        rc = _lib.load().lexbfs_batch_plan_launch(self.handle, _stream_handle(stream))
+        _lib.check(rc, "lexbfs_batch_plan_launch")
+
+    def results(self) -> List[Result]:
+        host = self.res.cpu()
+        out = []
+        for i, g in enumerate(self.graphs):
+            chordal, wit, clen, fb = _result_from(host[i])
+            kw = {k: v[: g.n] for k, v in self.tens[i].items()} if self.tens else {}
+            out.append(Result(chordal, wit, clen, fb, **kw))
+        return out
+
+    def close(self):
+        if self.handle:
+            _lib.load().lexbfs_batch_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,9 +24,13 @@ LEXBFS_EGRAPH = -4
 LEXBFS_ETOOBIG = -5
 LEXBFS_MAX_N = 65536
 LEXBFS_FLAG_FORCE_FALLBACK = 0x1
+LEXBFS_KERNEL_KINDS = 4
+KERNEL_KIND_NAMES = ("lexbfs", "sweep", "certificate", "setup")
 
 EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_order", "chordal_test", "lexbfs_batch_workspace_bytes",
-            "chordal_test_batch", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_abi_version"]
+            "chordal_test_batch", "lexbfs_batch_plan_create", "lexbfs_batch_plan_launch",
+            "lexbfs_batch_plan_destroy", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_profile_enable",
+            "lexbfs_profile_collect", "lexbfs_abi_version"]
 
 
 class lexbfs_graph_t(ctypes.Structure):
@@ -89,10 +93,22 @@ def load() -> ctypes.CDLL:
     lib.chordal_test_batch.restype = ctypes.c_int
     lib.chordal_test_batch.argtypes = [gp, ctypes.c_int32, ctypes.POINTER(lexbfs_outputs_t), vp,
                                        ctypes.POINTER(lexbfs_tuning_t), vp, sz, ctypes.c_uint32, vp]
+    lib.lexbfs_batch_plan_create.restype = ctypes.c_int
+    lib.lexbfs_batch_plan_create.argtypes = [gp, ctypes.c_int32, ctypes.POINTER(lexbfs_outputs_t), vp,
+                                             ctypes.POINTER(lexbfs_tuning_t), vp, sz, ctypes.c_uint32, vp,
+                                             ctypes.POINTER(ctypes.c_void_p)]
+    lib.lexbfs_batch_plan_launch.restype = ctypes.c_int
+    lib.lexbfs_batch_plan_launch.argtypes = [vp, vp]
+    lib.lexbfs_batch_plan_destroy.restype = None
+    lib.lexbfs_batch_plan_destroy.argtypes = [vp]
     lib.lexbfs_strerror.restype = ctypes.c_char_p
     lib.lexbfs_strerror.argtypes = [ctypes.c_int]
     lib.lexbfs_last_error.restype = ctypes.c_char_p
     lib.lexbfs_last_error.argtypes = []
+    lib.lexbfs_profile_enable.restype = ctypes.c_int
+    lib.lexbfs_profile_enable.argtypes = [ctypes.c_int]
+    lib.lexbfs_profile_collect.restype = ctypes.c_int
+    lib.lexbfs_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.lexbfs_abi_version.restype = ctypes.c_int
     lib.lexbfs_abi_version.argtypes = []
     _lib = lib

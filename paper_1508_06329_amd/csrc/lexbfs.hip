@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "lexbfs.h"
@@ -25,6 +26,7 @@ constexpr int kAbiVersion = 1;
 constexpr size_t kAlign = 256;
 constexpr int kSweepThreads = 256;
 constexpr int kFinishThreads = 256;
+constexpr int kBatchThreads = 256;
 
 // Description of the last failure on this thread (lexbfs_last_error).
 thread_local char t_last_error[256] = "";
@@ -46,6 +48,47 @@ int fail_code(int code, const char *what)
         const hipError_t e_ = hipGetLastError();                \
         if (e_ != hipSuccess) return fail_hip(e_, where);       \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel timing: while enabled, every launch is bracketed by a pair of HIP
+// events on its stream (events are created when timing is switched on, so
+// the launch path itself creates nothing).
+// ---------------------------------------------------------------------------
+constexpr int kKinds = LEXBFS_KERNEL_KINDS;
+constexpr int kProfPairs = 8192;
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    bool created = false;
+    hipEvent_t ev[2 * kProfPairs];
+    int kind[kProfPairs];
+    int used = 0;
+    int dropped = 0;
+};
+Profiler g_prof;
+
+struct ProfScope {
+    int slot = -1;
+    hipStream_t s;
+    ProfScope(int k, hipStream_t st) : s(st)
+    {
+        if (!g_prof.on) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.on) return;
+        if (g_prof.used >= kProfPairs) {
+            ++g_prof.dropped;
+            return;
+        }
+        slot = g_prof.used++;
+        g_prof.kind[slot] = k;
+        (void)hipEventRecord(g_prof.ev[2 * slot], s);
+    }
+    ~ProfScope()
+    {
+        if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+    }
+};
 
 // Everything a kernel needs about one graph (device copy for batches).
 struct GDesc {
@@ -300,20 +343,24 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags)
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <int T, bool kGlobal>
+// State placement of a single-graph LexBFS launch.
+enum : int { kModeLdsRem = 0, kModeLds = 1, kModeGlobal = 2 };
+
+template <int T, int kMode>
 __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
 {
     extern __shared__ uint64_t lds[];
     if (threadIdx.x == 0 && g.failkey) *g.failkey = kNoFail;
-    if (kGlobal) {
+    if (kMode == kModeGlobal) {
         LdsLayoutG L = carve_lds_g(lds, g.n, T);
         GlobalTables tab{g.gtab, g.gtab + g.n};
         BlockTeam<T, true> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, tab, L.red);
+        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, nullptr, tab, L.red);
     } else {
-        LdsLayout L = carve_lds(lds, g.n, T);
+        constexpr bool kRem = kMode == kModeLdsRem;
+        LdsLayout<kRem> L = carve_lds<kRem>(lds, g.n, T);
         BlockTeam<T, false> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, L.tab, L.red);
+        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
     }
 }
 
@@ -344,9 +391,9 @@ __global__ __launch_bounds__(BT) void k_lexbfs_batch(const GDesc *__restrict__ g
         __syncthreads();
         if (k >= nbig) break;
         const GDesc g = gds[sorted[k]];
-        LdsLayout L = carve_lds(lds, g.n, BT);
+        LdsLayout<true> L = carve_lds<true>(lds, g.n, BT);
         BlockTeam<BT, false> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, L.tab, L.red);
+        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
         __syncthreads();
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -358,9 +405,9 @@ __global__ __launch_bounds__(BT) void k_lexbfs_batch(const GDesc *__restrict__ g
         k = __shfl(k, 0, kWave);
         if (k >= nsmall) break;
         const GDesc g = gds[sorted[nbig + k]];
-        LdsLayout L = carve_lds(region, g.n, kWave);
+        LdsLayout<true> L = carve_lds<true>(region, g.n, kWave);
         WaveTeam tm{lane};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, L.unm, L.cls, L.tab, L.red);
+        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
         tm.sync();
     }
 }
@@ -500,16 +547,21 @@ SingleWs single_layout(int n)
 template <int T>
 int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
 {
-    const size_t lim_lds = dynamic_lds_limit(k_lexbfs_single<T, false>);
-    const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, true>);
-    if (!lim_lds || !lim_g) return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
-    const size_t b_lds = lds_bytes_lds_tables(d.n, T);
-    if (b_lds <= lim_lds) {
-        hipLaunchKernelGGL((k_lexbfs_single<T, false>), dim3(1), dim3(T), b_lds, s, d);
+    const size_t lim_r = dynamic_lds_limit(k_lexbfs_single<T, kModeLdsRem>);
+    const size_t lim_l = dynamic_lds_limit(k_lexbfs_single<T, kModeLds>);
+    const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, kModeGlobal>);
+    if (!lim_r || !lim_l || !lim_g) return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
+    const size_t b_r = lds_bytes_lds_tables(d.n, T, true);
+    const size_t b_l = lds_bytes_lds_tables(d.n, T, false);
+    const size_t b_g = lds_bytes_global_tables(d.n, T);
+    ProfScope ps(0, s);
+    if (b_r <= lim_r) {
+        hipLaunchKernelGGL((k_lexbfs_single<T, kModeLdsRem>), dim3(1), dim3(T), b_r, s, d);
+    } else if (b_l <= lim_l) {
+        hipLaunchKernelGGL((k_lexbfs_single<T, kModeLds>), dim3(1), dim3(T), b_l, s, d);
     } else {
-        const size_t b_g = lds_bytes_global_tables(d.n, T);
         if (b_g > lim_g) return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
-        hipLaunchKernelGGL((k_lexbfs_single<T, true>), dim3(1), dim3(T), b_g, s, d);
+        hipLaunchKernelGGL((k_lexbfs_single<T, kModeGlobal>), dim3(1), dim3(T), b_g, s, d);
     }
     LX_CHECK_LAUNCH("LexBFS launch");
     return LEXBFS_OK;
@@ -601,6 +653,21 @@ BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
 
 }  // namespace
 
+// A prepared batch: the descriptor table lives in the workspace; the host
+// keeps the launch shape.
+struct lexbfs_batch_plan {
+    int count = 0;
+    uint32_t flags = 0;
+    char *ws = nullptr;
+    BatchWs L{};
+    std::vector<char> table;
+    int nbig = 0;
+    int nitems = 0;
+    size_t lds = 0;
+    int region = 0;
+    int blocks = 1;
+};
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -609,6 +676,43 @@ extern "C" {
 int lexbfs_abi_version(void) { return kAbiVersion; }
 
 const char *lexbfs_last_error(void) { return t_last_error; }
+
+int lexbfs_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (on && !g_prof.created) {
+        for (int i = 0; i < 2 * kProfPairs; ++i) {
+            const hipError_t e = hipEventCreate(&g_prof.ev[i]);
+            if (e != hipSuccess) return fail_hip(e, "creating timing events");
+        }
+        g_prof.created = true;
+    }
+    g_prof.on = on != 0;
+    return LEXBFS_OK;
+}
+
+int lexbfs_profile_collect(int32_t *counts, double *ms)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (int k = 0; k < kKinds; ++k) {
+        if (counts) counts[k] = 0;
+        if (ms) ms[k] = 0.0;
+    }
+    for (int i = 0; i < g_prof.used; ++i) {
+        hipError_t e = hipEventSynchronize(g_prof.ev[2 * i + 1]);
+        if (e != hipSuccess) return fail_hip(e, "waiting for a timing event");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]);
+        if (e != hipSuccess) return fail_hip(e, "reading a timing event");
+        const int k = g_prof.kind[i];
+        if (counts) counts[k] += 1;
+        if (ms) ms[k] += t;
+    }
+    const int dropped = g_prof.dropped;
+    g_prof.used = 0;
+    g_prof.dropped = 0;
+    return dropped;
+}
 
 const char *lexbfs_strerror(int code)
 {
@@ -655,10 +759,16 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
         int G, lg;
         sweep_shape(d.wn, G, lg);
         const int rpb = sweep_rows_per_block(G);
-        hipLaunchKernelGGL(k_sweep_single, dim3((d.n + rpb - 1) / rpb), dim3(kSweepThreads), 0, s, d, rpb, G, lg);
+        {
+            ProfScope ps(1, s);
+            hipLaunchKernelGGL(k_sweep_single, dim3((d.n + rpb - 1) / rpb), dim3(kSweepThreads), 0, s, d, rpb, G, lg);
+        }
         LX_CHECK_LAUNCH("sweep launch");
     }
-    hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), 0, s, d, flags);
+    {
+        ProfScope ps(2, s);
+        hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), 0, s, d, flags);
+    }
     LX_CHECK_LAUNCH("certificate launch");
     return LEXBFS_OK;
 }
@@ -669,13 +779,14 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
     return batch_layout(gs, count).total;
 }
 
-int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
-                       lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
-                       uint32_t flags, void *stream)
+int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
+                             lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
+                             uint32_t flags, void *stream, lexbfs_batch_plan_t **plan_out)
 {
+    if (!plan_out) return LEXBFS_EINVAL;
+    *plan_out = nullptr;
     if (count < 0 || (count > 0 && (!gs || !res))) return LEXBFS_EINVAL;
-    if (count == 0) return LEXBFS_OK;
-    constexpr int BT = 256;
+    constexpr int BT = kBatchThreads;
     int wave_max_n = 1024;
     if (tuning) {
         if (tuning->block_threads != 0 && tuning->block_threads != BT) return LEXBFS_EINVAL;
@@ -692,19 +803,35 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
     if (maxn_block > 64 * BT) return fail_code(LEXBFS_ETOOBIG, "a batch graph exceeds 64 vertices per lane");
     const BatchWs L = batch_layout(gs, count);
     if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    lexbfs_batch_plan_t *P = new (std::nothrow) lexbfs_batch_plan_t();
+    if (!P) return fail_code(LEXBFS_EINVAL, "out of host memory for the batch plan");
+    P->count = count;
+    P->flags = flags;
+    P->ws = (char *)ws;
+    P->L = L;
+    if (count == 0) {
+        *plan_out = P;
+        return LEXBFS_OK;
+    }
     const size_t maxl = dynamic_lds_limit(k_lexbfs_batch<BT>);
-    if (!maxl) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
-    const size_t region = maxn_wave > 0 ? lds_bytes_lds_tables(maxn_wave, kWave) : 0;
-    size_t lds = std::max(lds_bytes_lds_tables(std::max(maxn_block, 1), BT), region * (BT / kWave));
+    if (!maxl) {
+        delete P;
+        return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
+    }
+    const size_t region = maxn_wave > 0 ? lds_bytes_lds_tables(maxn_wave, kWave, true) : 0;
+    size_t lds = std::max(lds_bytes_lds_tables(std::max(maxn_block, 1), BT, true), region * (BT / kWave));
     if (tuning && tuning->lds_bytes > 0) lds = std::max(lds, (size_t)tuning->lds_bytes);
-    if (lds > maxl) return fail_code(LEXBFS_ETOOBIG, "batch graph state does not fit the workgroup LDS");
+    if (lds > maxl) {
+        delete P;
+        return fail_code(LEXBFS_ETOOBIG, "batch graph state does not fit the workgroup LDS");
+    }
     char *w = (char *)ws;
 
     // Host plan: descriptors, longest-first order, sweep items.
-    std::vector<char> plan(L.failkeys - L.gds);
-    GDesc *hd = (GDesc *)plan.data();
-    int32_t *hsorted = (int32_t *)(plan.data() + (L.sorted - L.gds));
-    SweepItem *hitems = (SweepItem *)(plan.data() + (L.items - L.gds));
+    P->table.resize(L.failkeys - L.gds);
+    GDesc *hd = (GDesc *)P->table.data();
+    int32_t *hsorted = (int32_t *)(P->table.data() + (L.sorted - L.gds));
+    SweepItem *hitems = (SweepItem *)(P->table.data() + (L.items - L.gds));
     size_t aoff = L.arrays;
     for (int i = 0; i < count; ++i) {
         const lexbfs_graph_t &g = gs[i];
@@ -751,32 +878,75 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
         const int rpb = sweep_rows_per_block(G);
         for (int r0 = 0; r0 < n; r0 += rpb) hitems[it++] = SweepItem{i, r0, std::min(n, r0 + rpb), 0};
     }
-    hipStream_t s = (hipStream_t)stream;
-    {
-        const hipError_t e = hipMemcpyAsync(w + L.gds, plan.data(), plan.size(), hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return fail_hip(e, "staging the batch plan");
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
+    P->nbig = nbig;
+    P->nitems = it;
+    P->lds = lds;
+    P->region = (int)region;
+    P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
+    const hipError_t e =
+        hipMemcpyAsync(w + L.gds, P->table.data(), P->table.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        delete P;
+        return fail_hip(e, "staging the batch plan");
     }
-    const GDesc *dg = (const GDesc *)(w + L.gds);
-    uint32_t *qctr = (uint32_t *)(w + L.qctr);
-    hipLaunchKernelGGL(k_batch_init, dim3((count + 255) / 256), dim3(256), 0, s, dg, count, qctr);
+    *plan_out = P;
+    return LEXBFS_OK;
+}
+
+int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
+{
+    if (!P) return LEXBFS_EINVAL;
+    if (P->count == 0) return LEXBFS_OK;
+    constexpr int BT = kBatchThreads;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = P->ws;
+    const GDesc *dg = (const GDesc *)(w + P->L.gds);
+    uint32_t *qctr = (uint32_t *)(w + P->L.qctr);
+    {
+        ProfScope ps(3, s);
+        hipLaunchKernelGGL(k_batch_init, dim3((P->count + 255) / 256), dim3(256), 0, s, dg, P->count, qctr);
+    }
     LX_CHECK_LAUNCH("batch init launch");
     {
-        int cus = 256;
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-        const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
-        const int blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
-        hipLaunchKernelGGL((k_lexbfs_batch<BT>), dim3(blocks), dim3(BT), lds, s, dg,
-                           (const int32_t *)(w + L.sorted), nbig, count, qctr, (int)region);
-        LX_CHECK_LAUNCH("batch LexBFS launch");
+        ProfScope ps(0, s);
+        hipLaunchKernelGGL((k_lexbfs_batch<BT>), dim3(P->blocks), dim3(BT), P->lds, s, dg,
+                           (const int32_t *)(w + P->L.sorted), P->nbig, P->count, qctr, P->region);
     }
-    if (it > 0) {
-        hipLaunchKernelGGL(k_sweep_batch, dim3(it), dim3(kSweepThreads), 0, s, dg, (const SweepItem *)(w + L.items));
+    LX_CHECK_LAUNCH("batch LexBFS launch");
+    if (P->nitems > 0) {
+        {
+            ProfScope ps(1, s);
+            hipLaunchKernelGGL(k_sweep_batch, dim3(P->nitems), dim3(kSweepThreads), 0, s, dg,
+                               (const SweepItem *)(w + P->L.items));
+        }
         LX_CHECK_LAUNCH("batch sweep launch");
     }
-    hipLaunchKernelGGL(k_finish_batch, dim3(count), dim3(kFinishThreads), 0, s, dg, flags);
+    {
+        ProfScope ps(2, s);
+        hipLaunchKernelGGL(k_finish_batch, dim3(P->count), dim3(kFinishThreads), 0, s, dg, P->flags);
+    }
     LX_CHECK_LAUNCH("batch certificate launch");
     return LEXBFS_OK;
+}
+
+void lexbfs_batch_plan_destroy(lexbfs_batch_plan_t *plan) { delete plan; }
+
+int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
+                       lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
+                       uint32_t flags, void *stream)
+{
+    if (count == 0 && count >= 0) return LEXBFS_OK;
+    lexbfs_batch_plan_t *P = nullptr;
+    int rc = lexbfs_batch_plan_create(gs, count, outs, res, tuning, ws, ws_bytes, flags, stream, &P);
+    if (rc) return rc;
+    rc = lexbfs_batch_plan_launch(P, stream);
+    lexbfs_batch_plan_destroy(P);
+    return rc;
 }
 
 }  // extern "C"

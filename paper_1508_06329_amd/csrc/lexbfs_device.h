@@ -19,9 +19,6 @@
 // first position s. Per vertex we keep only cls[v] = s; per class the last
 // position clast[s] and a split counter cnt[s].
 //
-//   * Pivot: the unnumbered vertex with the largest (cls, -id) -- the
-//     largest label, smallest id on ties. One max-reduction over a packed
-//     32-bit key (cls << 16 | 0xFFFF - v).
 //   * Removing the pivot from the top class [s, U) shrinks it to [s, U-1).
 //   * Appending the step number to the labels of the pivot's unnumbered
 //     neighbours splits each class C = [s, last] hit by c neighbours into
@@ -33,6 +30,35 @@
 //   * Empty classes cannot occur except at the top, so the paper's
 //     empty-set removal pass (Lemma 6.3) has no counterpart.
 //   * Every id stays below U <= n <= 65536, so classes fit in 16 bits.
+//
+// Next pivot without a scan. After step i the largest label belongs to the
+// highest pre-split class C_top among the unnumbered vertices, narrowed to
+// C_top & N(x_i) when that is not empty (the split puts that part directly
+// above the rest of C_top; every other class stays below C_top). Every lane
+// keeps, as a bitmask over its own vertices, the members of the current top
+// class. Then with T' = top \ {x_i}:
+//   T' & N(x_i) not empty -> x_{i+1} = its smallest id, top = T' & N(x_i);
+//   else T' not empty     -> x_{i+1} = smallest id of T', top = T';
+//   else                  -> the top class is exhausted: its successor C_1
+//                            is the highest live class start (a bitmap of
+//                            class starts is kept in LDS), each lane matches
+//                            its vertices against C_1, and the rule above is
+//                            applied to C_1.
+// The first two cases cost a few bit operations and one 32-bit max per
+// step; only the third touches every vertex of a lane. Both use pre-split
+// information only, so x_{i+1} is known as soon as x_i's row is in, and the
+// load of x_{i+1}'s row is issued before the splits of step i run.
+//
+// A pivot none of whose neighbours is still unnumbered causes no split; a
+// per-vertex count rem[v] of unnumbered neighbours (decremented during the
+// splits) lets the team skip loading such a pivot's row and the barrier
+// after the (empty) split phase.
+//
+// Closing a split class without a third barrier: every neighbour of class C
+// reads C's neighbour count and clast[C], then counts itself as moved with
+// an atomic add; the one that moves last -- after every other neighbour has
+// read -- writes the shrunken clast[C], marks the new class start and
+// clears the counters for the next step.
 //
 // The last pivot adjacent to y before y is numbered is y's latest earlier
 // neighbour, so parent[y] (p(y) of Section 5.2) is recorded during the
@@ -72,14 +98,45 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+// One DPP step of a 64-bit max scan: every lane takes the max of its value
+// and the value DPP control CTRL routes to it (0 where nothing is routed).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_max64_step(uint64_t v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, kWave);
-    return v;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xF, true);
+    const uint64_t o = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    return o > v ? o : v;
+}
+
+// Max over the 64 lanes (all lanes must be active); the result is uniform.
+// Row shifts 1, 2, 4, 8 leave each 16-lane row's maximum in its lane 15;
+// the row broadcasts 15 and 31 then carry it to lane 63.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+    v = dpp_max64_step<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_max64_step<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_max64_step<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_max64_step<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_max64_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max64_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ int ctz64(uint64_t x) { return __builtin_ctzll(x); }
+
+// Pointers read from memory (batch descriptors) are generic to the compiler,
+// which then emits flat instructions; those count against the LDS counter as
+// well, so every LDS wait would also wait for outstanding row loads and
+// stores. All graph and output arrays live in global memory: say so.
+#define LX_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ LX_GLOBAL T *as_global(T *p)
+{
+    return (LX_GLOBAL T *)p;
+}
 
 // ---------------------------------------------------------------------------
 // Agent-scope accessors for scratch tables in global memory. Waves of one
@@ -106,9 +163,30 @@ __device__ __forceinline__ void g_store_i(int32_t *p, int32_t v)
 // ---------------------------------------------------------------------------
 // Teams
 // ---------------------------------------------------------------------------
+// Max of a 32-bit value over the 64 lanes with DPP (all lanes active); the
+// result is uniform.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_max32_step(uint32_t v)
+{
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+    return o > v ? o : v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_dpp(uint32_t v)
+{
+    v = dpp_max32_step<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_max32_step<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_max32_step<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_max32_step<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_max32_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max32_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 struct WaveTeam {
     int tid;  // lane
     static constexpr int kSize = kWave;
+    static constexpr int kWaves = 1;
     __device__ __forceinline__ void sync() const
     {
         // LDS operations of one wave complete in issue order; this only has to
@@ -117,123 +195,210 @@ struct WaveTeam {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __device__ __forceinline__ uint32_t max_all(uint32_t v, uint32_t *) const { return wave_max_u32(v); }
-    __device__ __forceinline__ void step_end() const { sync(); }
+    __device__ __forceinline__ uint32_t max_all(uint32_t v, uint32_t *) const
+    {
+        v = wave_max_dpp(v);
+        sync();
+        return v;
+    }
 };
 
+// On gfx950 a workgroup barrier waits for LDS traffic only; global loads in
+// flight (the prefetched pivot row) stay in flight across it. With the class
+// tables in global memory the barrier also orders those accesses (agent
+// fences), which does wait for every outstanding memory operation.
 template <int T, bool kGlobalTables>
 struct BlockTeam {
     int tid;
     static constexpr int kSize = T;
+    static constexpr int kWaves = T / kWave;
     __device__ __forceinline__ void sync() const
     {
         if (kGlobalTables) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (kGlobalTables) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    // Max over the team; every lane gets the result. red: T/64 LDS words.
+    // Max over the team (one barrier); every lane gets the result.
+    // red: T/64 LDS words, not reused before the next barrier.
     __device__ __forceinline__ uint32_t max_all(uint32_t v, uint32_t *red) const
     {
-        v = wave_max_u32(v);
+        v = wave_max_dpp(v);
         if ((tid & 63) == 0) red[tid >> 6] = v;
         sync();
         uint32_t r = red[0];
 #pragma unroll
-        for (int k = 1; k < T / kWave; ++k) r = max(r, red[k]);
+        for (int k = 1; k < kWaves; ++k) r = max(r, red[k]);
         return r;
     }
-    // The barrier inside max_all already separates consecutive steps.
-    __device__ __forceinline__ void step_end() const {}
 };
 
 // ---------------------------------------------------------------------------
-// Class tables (clast, cnt): in LDS when they fit, else in global scratch.
+// Class tables. Per class c: clast[c], the last position of the class, and
+// a 32-bit split word whose low half counts the pivot's neighbours in c
+// (phase A) and whose high half counts those that have already moved
+// (phase B). The low half is final and stable throughout phase B; the
+// neighbour that moves last (high half reaching the count) closes the class
+// and clears the word for the next step.
+// LDS form: clast 16-bit, optional rem; global form (large n): 32-bit
+// entries in L2, no rem.
 // ---------------------------------------------------------------------------
+template <bool kWithRem>
 struct LdsTables {
     uint16_t *clast;
     uint32_t *cnt;
+    static constexpr bool kRem = kWithRem;
     __device__ __forceinline__ uint32_t last(uint32_t c) const { return clast[c]; }
     __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { clast[c] = (uint16_t)v; }
-    __device__ __forceinline__ uint32_t count(uint32_t c) const { return cnt[c]; }
-    __device__ __forceinline__ void set_count(uint32_t c, uint32_t v) const { cnt[c] = v; }
-    __device__ __forceinline__ uint32_t add(uint32_t c, uint32_t v) const { return atomicAdd(&cnt[c], v); }
+    __device__ __forceinline__ uint32_t word(uint32_t c) const { return cnt[c]; }
+    __device__ __forceinline__ void clear(uint32_t c) const { cnt[c] = 0u; }
+    __device__ __forceinline__ void inc(uint32_t c) const { atomicAdd(&cnt[c], 1u); }
+    // Count one neighbour as moved; returns the word before.
+    __device__ __forceinline__ uint32_t moved(uint32_t c) const { return atomicAdd(&cnt[c], 0x10000u); }
 };
 
 struct GlobalTables {
     uint32_t *clast;
     uint32_t *cnt;
+    static constexpr bool kRem = false;
     __device__ __forceinline__ uint32_t last(uint32_t c) const { return g_load(&clast[c]); }
     __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { g_store(&clast[c], v); }
-    __device__ __forceinline__ uint32_t count(uint32_t c) const { return g_load(&cnt[c]); }
-    __device__ __forceinline__ void set_count(uint32_t c, uint32_t v) const { g_store(&cnt[c], v); }
-    __device__ __forceinline__ uint32_t add(uint32_t c, uint32_t v) const
+    __device__ __forceinline__ uint32_t word(uint32_t c) const { return g_load(&cnt[c]); }
+    __device__ __forceinline__ void clear(uint32_t c) const { g_store(&cnt[c], 0u); }
+    __device__ __forceinline__ void inc(uint32_t c) const
     {
-        return __hip_atomic_fetch_add(&cnt[c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ uint32_t moved(uint32_t c) const
+    {
+        return __hip_atomic_fetch_add(&cnt[c], 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
-// LDS bytes of the LexBFS state for n vertices.
 __host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-__host__ __device__ inline size_t lds_bytes_lds_tables(int n, int team)
+// LDS of one graph's state. Tables in LDS:
+//   starts u64[wn] | red u32[2 waves] | cls u16[n] | clast u16[n] | cnt u32[n] | rem u16[n] (optional)
+// Tables in global memory:
+//   starts u64[wn] | red u32[2 waves] | cls u16[n]
+// Every array starts on a 16-byte boundary (cls is read 16 bytes at a time).
+__host__ __device__ inline size_t lds_bytes_lds_tables(int n, int team, bool with_rem)
 {
     const size_t wn = (size_t)(n + 63) / 64;
-    return align_up(8 * wn + 4 * (size_t)(team / kWave > 0 ? team / kWave : 1) + 4 * (size_t)n + 2 * align_up(n, 2) * 2, 16);
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    const size_t a = align_up(2 * (size_t)n, 16);
+    return align_up(8 * wn, 16) + align_up(8 * nred, 16) + 2 * a + align_up(4 * (size_t)n, 16) + (with_rem ? a : 0);
 }
 
 __host__ __device__ inline size_t lds_bytes_global_tables(int n, int team)
 {
     const size_t wn = (size_t)(n + 63) / 64;
-    return align_up(8 * wn + 4 * (size_t)(team / kWave > 0 ? team / kWave : 1) + 2 * align_up(n, 2), 16);
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    return align_up(8 * wn, 16) + align_up(8 * nred, 16) + align_up(2 * (size_t)n, 16);
 }
 
-// Carve the LDS region of one graph (tables in LDS).
+template <bool kWithRem>
 struct LdsLayout {
-    uint64_t *unm;
+    uint64_t *starts;
     uint32_t *red;
     uint16_t *cls;
-    LdsTables tab;
+    uint16_t *rem;
+    LdsTables<kWithRem> tab;
 };
 
-__device__ __forceinline__ LdsLayout carve_lds(void *base, int n, int team)
+template <bool kWithRem>
+__device__ __forceinline__ LdsLayout<kWithRem> carve_lds(void *base, int n, int team)
 {
-    const int wn = (n + 63) >> 6;
-    LdsLayout L;
-    L.unm = (uint64_t *)base;
-    L.red = (uint32_t *)(L.unm + wn);
-    const int nred = team / kWave > 0 ? team / kWave : 1;
-    L.tab.cnt = L.red + nred;
-    L.cls = (uint16_t *)(L.tab.cnt + n);
-    L.tab.clast = L.cls + ((n + 1) & ~1);
+    const size_t wn = (size_t)(n + 63) / 64;
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    const size_t a = align_up(2 * (size_t)n, 16);
+    char *p = (char *)base;
+    LdsLayout<kWithRem> L;
+    L.starts = (uint64_t *)p;
+    p += align_up(8 * wn, 16);
+    L.red = (uint32_t *)p;
+    p += align_up(8 * nred, 16);
+    L.cls = (uint16_t *)p;
+    L.tab.clast = (uint16_t *)(p + a);
+    L.tab.cnt = (uint32_t *)(p + 2 * a);
+    L.rem = kWithRem ? (uint16_t *)(p + 2 * a + align_up(4 * (size_t)n, 16)) : nullptr;
     return L;
 }
 
 struct LdsLayoutG {
-    uint64_t *unm;
+    uint64_t *starts;
     uint32_t *red;
     uint16_t *cls;
 };
 
 __device__ __forceinline__ LdsLayoutG carve_lds_g(void *base, int n, int team)
 {
-    const int wn = (n + 63) >> 6;
+    const size_t wn = (size_t)(n + 63) / 64;
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    char *p = (char *)base;
     LdsLayoutG L;
-    L.unm = (uint64_t *)base;
-    L.red = (uint32_t *)(L.unm + wn);
-    const int nred = team / kWave > 0 ? team / kWave : 1;
-    L.cls = (uint16_t *)(L.red + nred);
+    L.starts = (uint64_t *)p;
+    p += align_up(8 * wn, 16);
+    L.red = (uint32_t *)p;
+    p += align_up(8 * nred, 16);
+    L.cls = (uint16_t *)p;
     return L;
+}
+
+// Bits of my unnumbered vertices `um` (word positions) whose class is c.
+__device__ __forceinline__ uint64_t chunk_match(const uint16_t *cls, uint64_t um, uint32_t c, int vbase, int sh, int K)
+{
+    if (!um) return 0;
+    uint64_t res = 0;
+    if (K >= 8) {
+        const uint32_t pat = c | (c << 16);
+        const uint4 *p = (const uint4 *)(cls + vbase);
+        for (int j = 0; j < K; j += 8) {
+            if (!((um >> (sh + j)) & 0xFFull)) continue;
+            const uint4 q = p[j >> 3];
+            const uint32_t x0 = q.x ^ pat, x1 = q.y ^ pat, x2 = q.z ^ pat, x3 = q.w ^ pat;
+            const uint32_t m8 = ((x0 & 0xFFFFu) == 0) | ((x0 >> 16) == 0) << 1 | ((x1 & 0xFFFFu) == 0) << 2 |
+                                ((x1 >> 16) == 0) << 3 | ((x2 & 0xFFFFu) == 0) << 4 | ((x2 >> 16) == 0) << 5 |
+                                ((x3 & 0xFFFFu) == 0) << 6 | ((x3 >> 16) == 0) << 7;
+            res |= (uint64_t)m8 << (sh + j);
+        }
+        return res & um;
+    }
+    const int wbase = (vbase >> 6) << 6;
+    for (uint64_t m = um; m; m &= m - 1) {
+        const int b = ctz64(m);
+        if (cls[wbase + b] == c) res |= 1ull << b;
+    }
+    return res;
+}
+
+// Selection key: case 2 (pivot-adjacent part of the top class) above case 1
+// (rest of the top class), then the smallest id.
+__device__ __forceinline__ uint32_t pick_key(uint64_t top, uint64_t nb, uint32_t wbase)
+{
+    const uint64_t a = top & nb;
+    if (a) return 0x20000u | (0xFFFFu - (wbase + (uint32_t)ctz64(a)));
+    if (top) return 0x10000u | (0xFFFFu - (wbase + (uint32_t)ctz64(top)));
+    return 0u;
 }
 
 // ---------------------------------------------------------------------------
 // LexBFS on one graph by one team.
+//   row_ptr is read once (initial rem = degree) when the tables are in LDS.
+//   red: 2 * waves LDS words (alternating between consecutive reductions).
 // ---------------------------------------------------------------------------
 template <class Team, class Tabs>
-__device__ void lexbfs_team(const Team &tm, int n, const uint64_t *__restrict__ bits, int64_t W,
-                            int32_t *__restrict__ order, int32_t *__restrict__ rank, int32_t *__restrict__ parent,
-                            uint64_t *unm, uint16_t *cls, const Tabs &tab, uint32_t *red)
+__device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
+                            int32_t *order_, int32_t *rank_, int32_t *parent_, uint64_t *starts, uint16_t *cls,
+                            uint16_t *rem, const Tabs &tab, uint32_t *red)
 {
+    LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
+    LX_GLOBAL const int32_t *__restrict__ row_ptr = as_global(row_ptr_);
+    LX_GLOBAL int32_t *__restrict__ order = as_global(order_);
+    LX_GLOBAL int32_t *__restrict__ rank = as_global(rank_);
+    LX_GLOBAL int32_t *__restrict__ parent = as_global(parent_);
     constexpr int T = Team::kSize;
+    constexpr int NW = Team::kWaves;
+    constexpr bool kRem = Tabs::kRem;
     const int t = tm.tid;
     if (n <= 0) return;
     const int wn = (n + 63) >> 6;
@@ -242,93 +407,108 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *__restrict__ 
     const int vbase = t * K;
     const int wi = vbase >> 6;
     const int sh = vbase & 63;
-    const uint64_t cmask = (K == 64) ? ~0ull : (((1ull << K) - 1ull) << sh);
+    const uint32_t wbase = (uint32_t)wi << 6;
+    uint64_t cmask = (K == 64) ? ~0ull : (((1ull << K) - 1ull) << sh);
+    if (wi == wn - 1 && (n & 63)) cmask &= (1ull << (n & 63)) - 1ull;
     const bool owner = vbase < n;
+    LX_GLOBAL const uint64_t *rowbase = bits + wi;
 
     for (int v = t; v < n; v += T) {
         cls[v] = 0;
-        tab.set_count(v, 0);
+        tab.clear(v);
+        if (kRem) rem[v] = (uint16_t)(row_ptr[v + 1] - row_ptr[v]);
     }
+    for (int w = t; w < wn; w += T) starts[w] = w == 0 ? 1ull : 0ull;  // one class, starting at 0
     // parent[v] is later written only by v's owner lane; the same lane clears it.
     if (owner)
         for (int v = vbase; v < min(vbase + K, n); ++v) parent[v] = -1;
-    for (int w = t; w < wn; w += T) unm[w] = (w == wn - 1 && (n & 63)) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
     if (t == 0) tab.set_last(0, (uint32_t)(n - 1));
     tm.sync();
 
-    uint32_t x = 0;     // pivot: vertex 0 first (smallest id, all labels empty)
-    uint32_t stop = 0;  // its class
+    uint64_t um = owner ? cmask : 0ull;  // my unnumbered vertices (word positions)
+    uint64_t top = um;                   // my members of the top class
+    uint32_t x = 0;                      // first pivot: vertex 0 (smallest id, all labels empty)
+    bool xrem = !kRem || rem[0] > 0;     // does the pivot still have unnumbered neighbours?
+    uint64_t rw = (owner && xrem) ? rowbase[0] : 0ull;  // my chunk's word of the pivot's row
+    int par = 0;
     int U = n;
-    const uint64_t *rowbase = bits + wi;
     for (int i = 0; i < n; ++i) {
         U -= 1;
+        const uint32_t stop = cls[x];  // the pivot's (post-split) class
+        if (owner && (x >> 6) == (uint32_t)wi) {
+            um &= ~(1ull << (x & 63));
+            top &= ~(1ull << (x & 63));
+        }
+        uint64_t nb = rw & um;
+        // Global stores only after the row word is in: on gfx9 the memory
+        // counter covers stores too, so a store issued between the row load
+        // and its use would hold up the use until the store completes. The
+        // empty asm pins the use of the row here, ahead of the stores.
+        __asm__ volatile("" : "+v"(nb)::"memory");
         if (t == 0) {
+            if ((int)stop < U) tab.set_last(stop, (uint32_t)(U - 1));
+            else atomicAnd((unsigned long long *)&starts[stop >> 6], ~(1ull << (stop & 63)));  // class gone
             order[i] = (int32_t)x;
             rank[x] = i;
-            if ((int)stop < U) tab.set_last(stop, (uint32_t)(U - 1));
-            atomicAnd((unsigned long long *)&unm[x >> 6], ~(1ull << (x & 63)));
         }
-        uint64_t nb = 0;
-        if (owner) nb = rowbase[(int64_t)x * W] & unm[wi] & cmask;
 
         // Phase A: count the neighbours of every hit class; record the parent.
-        uint64_t lead = 0;
         for (uint64_t m = nb; m; m &= m - 1) {
-            const int b = ctz64(m);
-            const int y = (wi << 6) + b;
+            const int y = (int)wbase + ctz64(m);
             const uint32_t C = cls[y];
             parent[y] = (int32_t)x;
-            if (tab.add(C, 1) == 0) lead |= 1ull << b;
+            if (kRem) rem[y] = (uint16_t)(rem[y] - 1);
+            tab.inc(C);
         }
-        tm.sync();
+        if (i + 1 == n) break;
 
-        // Phase B: move the neighbours to the upper part of their class.
-        uint64_t split = 0;
+        // Next pivot (see the header comment).
+        uint32_t k = tm.max_all(pick_key(top, nb, wbase), red + par * NW);
+        par ^= 1;
+        if ((k >> 16) == 0) {
+            // The top class is exhausted: its successor is the highest live
+            // class start (the pivot's class was cleared above).
+            uint32_t hi = 0;
+            for (int w = t; w < wn; w += T) {
+                const uint64_t sw = starts[w];
+                if (sw) hi = max(hi, (uint32_t)((w << 6) | (63 - __builtin_clzll(sw))) + 1u);
+            }
+            const uint32_t c1 = tm.max_all(hi, red + par * NW) - 1u;
+            par ^= 1;
+            top = chunk_match(cls, um, c1, vbase, sh, K);
+            k = tm.max_all(pick_key(top, nb, wbase), red + par * NW);
+            par ^= 1;
+        }
+        const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
+        if ((k >> 16) == 2) top &= nb;  // narrowed to the pivot's neighbours
+        const bool nrem = !kRem || rem[xn] > 0;
+        const uint64_t rwn = (owner && nrem) ? rowbase[(int64_t)xn * W] : 0ull;
+
+        // Phase B: move the neighbours to the upper part of their class; the
+        // last neighbour of a class to leave closes it.
         for (uint64_t m = nb; m; m &= m - 1) {
-            const int b = ctz64(m);
-            const int y = (wi << 6) + b;
+            const int y = (int)wbase + ctz64(m);
             const uint32_t C = cls[y];
-            const uint32_t c = tab.count(C);
+            const uint32_t c = tab.word(C) & 0xFFFFu;  // final neighbour count of C
             const uint32_t last = tab.last(C);
-            if (c < last - C + 1) {
-                const uint32_t nw = last + 1 - c;
+            const bool split = c < last - C + 1;
+            const uint32_t nw = last + 1 - c;
+            if (split) {
                 cls[y] = (uint16_t)nw;
-                if ((lead >> b) & 1ull) {
-                    tab.set_last(nw, last);
-                    tab.set_count(nw, C);  // remember the old class for phase C
-                    split |= 1ull << b;
+                tab.set_last(nw, last);
+            }
+            if ((tab.moved(C) >> 16) == c - 1) {  // the last one out closes C
+                tab.clear(C);
+                if (split) {
+                    tab.set_last(C, nw - 1);
+                    atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
                 }
             }
         }
-        tm.sync();
-
-        // Phase C: the leader of each hit class closes it; then pick the pivot.
-        for (uint64_t m = lead; m; m &= m - 1) {
-            const int b = ctz64(m);
-            const int y = (wi << 6) + b;
-            const uint32_t nw = cls[y];
-            if ((split >> b) & 1ull) {
-                const uint32_t C = tab.count(nw);
-                tab.set_last(C, nw - 1);
-                tab.set_count(C, 0);
-                tab.set_count(nw, 0);
-            } else {
-                tab.set_count(nw, 0);
-            }
-        }
-        if (i + 1 == n) break;
-        uint32_t best = 0;
-        if (owner) {
-            for (uint64_t m = unm[wi] & cmask; m; m &= m - 1) {
-                const uint32_t v = (uint32_t)((wi << 6) + ctz64(m));
-                const uint32_t key = ((uint32_t)cls[v] << 16) | (0xFFFFu - v);
-                best = max(best, key);
-            }
-        }
-        best = tm.max_all(best, red);
-        x = 0xFFFFu - (best & 0xFFFFu);
-        stop = best >> 16;
-        tm.step_end();
+        if (xrem) tm.sync();  // barrier B: nothing to order when the pivot split nothing
+        x = xn;
+        rw = rwn;
+        xrem = nrem;
     }
 }
 
@@ -342,10 +522,14 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *__restrict__ 
 // a rank lookup. The smallest failing rank is kept with atomicMin.
 // A group of G lanes (a power of two <= 64) handles one row.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sweep_rows(const uint64_t *__restrict__ bits, int64_t W, int wn,
-                                           const int32_t *__restrict__ rank, const int32_t *__restrict__ parent,
-                                           int n, int r0, int r1, int G, int lg, uint32_t *failkey)
+__device__ __forceinline__ void sweep_rows(const uint64_t *bits_, int64_t W, int wn, const int32_t *rank_,
+                                           const int32_t *parent_, int n, int r0, int r1, int G, int lg,
+                                           uint32_t *failkey_)
 {
+    LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
+    LX_GLOBAL const int32_t *__restrict__ rank = as_global(rank_);
+    LX_GLOBAL const int32_t *__restrict__ parent = as_global(parent_);
+    LX_GLOBAL uint32_t *failkey = as_global(failkey_);
     const uint64_t tail = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
     const int lane = threadIdx.x & 63;
     const int gid = lane >> lg;
@@ -363,8 +547,8 @@ __device__ __forceinline__ void sweep_rows(const uint64_t *__restrict__ bits, in
             if (p >= 0) {
                 rv = rank[v];
                 const int rp = rank[p];
-                const uint64_t *a = bits + (int64_t)v * W;
-                const uint64_t *b = bits + (int64_t)p * W;
+                LX_GLOBAL const uint64_t *a = bits + (int64_t)v * W;
+                LX_GLOBAL const uint64_t *b = bits + (int64_t)p * W;
                 for (int w = gl; w < wn && !fail; w += G) {
                     uint64_t X = __builtin_nontemporal_load(a + w) & ~b[w];
                     if (w == wn - 1) X &= tail;  // ids >= n never index rank[]
@@ -377,7 +561,7 @@ __device__ __forceinline__ void sweep_rows(const uint64_t *__restrict__ bits, in
             }
         }
         const uint64_t bal = __ballot(fail);
-        if ((bal & gmask) && gl == 0) atomicMin(failkey, (uint32_t)rv);
+        if ((bal & gmask) && gl == 0) __hip_atomic_fetch_min(failkey, (uint32_t)rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "lexbfs.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char|void)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -106,8 +106,14 @@ def test_argument_errors(lib):
     arr = (_lib.lexbfs_graph_t * 1)(fake_graph(10))
     assert lib.chordal_test_batch(arr, 1, None, res, ctypes.byref(tun), ws, 1 << 30, 0, None) == _lib.LEXBFS_EINVAL
     small = lib.lexbfs_batch_workspace_bytes(arr, 1)
-    assert lib.chordal_test_batch(arr, 1, None, res, None, ws, 0, 0, None) in (_lib.LEXBFS_ENOWS, _lib.LEXBFS_EHIP)
+    assert lib.chordal_test_batch(arr, 1, None, res, None, ws, 0, 0, None) == _lib.LEXBFS_ENOWS
     assert small > 0
+    plan = ctypes.c_void_p()
+    assert lib.lexbfs_batch_plan_create(arr, 1, None, res, None, ws, 0, 0, None, None) == _lib.LEXBFS_EINVAL
+    assert lib.lexbfs_batch_plan_create(arr, 1, None, res, None, ws, 0, 0, None, ctypes.byref(plan)) == _lib.LEXBFS_ENOWS
+    assert not plan.value
+    assert lib.lexbfs_batch_plan_launch(None, None) == _lib.LEXBFS_EINVAL
+    lib.lexbfs_batch_plan_destroy(None)
 
 
 def test_workspace_sizes_grow(lib):
