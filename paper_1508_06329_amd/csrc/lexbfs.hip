@@ -159,60 +159,100 @@ __device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t *s)
 // smallest-id neighbour of the previous layer each time. Writes
 // path[0] = src .. path[d] = dst and returns d + 1, or 0 if unreachable.
 // All threads of the block call it with the same arguments.
+//
+// Layers are bitsets: a layer's successor is the OR of its vertices' rows,
+// masked by A and by the visited set. The block's waves split the frontier
+// (four rows in flight per wave), lanes split the words of a row, and the
+// partial layers meet in LDS through atomic ORs. Each newly reached vertex
+// gets level[u] = stamp << 16 | depth; stamps keep successive searches of
+// one call apart without clearing level[] between them.
+// LDS: amask, vis, nxt -- three bitsets of wn words each.
 // ---------------------------------------------------------------------------
 template <int T>
-__device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path)
+__device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path, uint64_t *amask, uint64_t *vis,
+                        uint64_t *nxt, uint32_t stamp)
 {
-    __shared__ int s_nq;
+    __shared__ int s_nf;
     __shared__ int s_pred;
-    const int tid = threadIdx.x;
-    const uint64_t *rowc = g.bits + (int64_t)c * g.W;
-    for (int u = tid; u < g.n; u += T) g_store_i(&g.level[u], -1);
-    block_sync_agent();
-    if (tid == 0) {
-        g_store_i(&g.level[src], 0);
-        g_store_i(&g.q0[0], src);
+    constexpr int NW = T / kWave;
+    LX_GLOBAL const uint64_t *bits = as_global(g.bits);
+    LX_GLOBAL const int32_t *rp = as_global(g.rp);
+    LX_GLOBAL const int32_t *ci = as_global(g.ci);
+    LX_GLOBAL int32_t *level = as_global(g.level);
+    LX_GLOBAL int32_t *q = as_global(g.q0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wn = g.wn;
+    const uint64_t tail = (g.n & 63) ? ((1ull << (g.n & 63)) - 1ull) : ~0ull;
+    LX_GLOBAL const uint64_t *rowc = bits + (int64_t)c * g.W;
+    for (int w = tid; w < wn; w += T) {
+        uint64_t a = ~rowc[w];
+        if (w == wn - 1) a &= tail;
+        if (w == (c >> 6)) a &= ~(1ull << (c & 63));
+        if (w == (src >> 6)) a |= 1ull << (src & 63);
+        if (w == (dst >> 6)) a |= 1ull << (dst & 63);
+        amask[w] = a;
+        vis[w] = w == (src >> 6) ? (1ull << (src & 63)) : 0ull;
+        nxt[w] = vis[w];
     }
-    block_sync_agent();
-    int qn = 1, d = 0;
-    int32_t *cur = g.q0, *nxt = g.q1;
-    const int wave = tid >> 6, lane = tid & 63;
-    while (qn > 0 && g_load_i(&g.level[dst]) < 0) {
-        if (tid == 0) s_nq = 0;
+    if (tid == 0) level[src] = (int32_t)(stamp << 16);
+    __syncthreads();
+    int d = 0;
+    for (;;) {
+        // The frontier (nxt) as a list of ids in q.
+        if (tid == 0) s_nf = 0;
         __syncthreads();
-        for (int f = wave; f < qn; f += T / kWave) {
-            const int u = g_load_i(&cur[f]);
-            const int e = g.rp[u + 1];
-            for (int j = g.rp[u] + lane; j < e; j += kWave) {
-                const int y = g.ci[j];
-                if ((unsigned)y >= (unsigned)g.n) continue;
-                const bool inA = (y == src) || (y == dst) || (y != c && !test_bit(rowc, y));
-                if (!inA || g_load_i(&g.level[y]) >= 0) continue;
-                if (cas_agent(&g.level[y], -1, d + 1) == -1) {
-                    const int pos = atomicAdd(&s_nq, 1);
-                    g_store_i(&nxt[pos], y);
-                }
-            }
+        for (int w = tid; w < wn; w += T) {
+            uint64_t f = nxt[w];
+            if (!f) continue;
+            int p = atomicAdd(&s_nf, __popcll(f));
+            for (; f; f &= f - 1) q[p++] = (w << 6) + ctz64(f);
         }
         block_sync_agent();
-        qn = s_nq;
-        int32_t *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-        ++d;
+        const int nf = s_nf;
+        if (nf == 0) return 0;  // dst unreachable
+        for (int w = tid; w < wn; w += T) nxt[w] = 0ull;
         __syncthreads();
+        // Next layer: OR of the frontier's rows, masked.
+        for (int f0 = wave; f0 < nf; f0 += 4 * NW) {
+            const int u0 = q[f0];
+            const int u1 = f0 + NW < nf ? q[f0 + NW] : -1;
+            const int u2 = f0 + 2 * NW < nf ? q[f0 + 2 * NW] : -1;
+            const int u3 = f0 + 3 * NW < nf ? q[f0 + 3 * NW] : -1;
+            for (int w = lane; w < wn; w += kWave) {
+                uint64_t acc = bits[(int64_t)u0 * g.W + w];
+                if (u1 >= 0) acc |= bits[(int64_t)u1 * g.W + w];
+                if (u2 >= 0) acc |= bits[(int64_t)u2 * g.W + w];
+                if (u3 >= 0) acc |= bits[(int64_t)u3 * g.W + w];
+                acc &= amask[w] & ~vis[w];
+                if (acc) atomicOr((unsigned long long *)&nxt[w], acc);
+            }
+        }
+        __syncthreads();
+        ++d;
+        int found = 0;
+        for (int w = tid; w < wn; w += T) {
+            const uint64_t nw = nxt[w];
+            if (!nw) continue;
+            vis[w] |= nw;
+            for (uint64_t m = nw; m; m &= m - 1) {
+                const int u = (w << 6) + ctz64(m);
+                level[u] = (int32_t)((stamp << 16) | (uint32_t)d);
+                found |= u == dst;
+            }
+        }
+        if (__syncthreads_or(found)) break;
     }
-    const int L = g_load_i(&g.level[dst]);
-    if (L < 0) return 0;
-    if (tid == 0) path[L] = dst;
+    block_sync_agent();  // levels visible to every lane
+    if (tid == 0) path[d] = dst;
     int y = dst;
-    for (int l = L; l >= 1; --l) {
+    for (int l = d; l >= 1; --l) {
         if (tid == 0) s_pred = INT_MAX;
         __syncthreads();
-        const int e = g.rp[y + 1];
-        for (int j = g.rp[y] + tid; j < e; j += T) {  // rows ascend: first hit per lane is its minimum
-            const int u = g.ci[j];
-            if ((unsigned)u < (unsigned)g.n && g_load_i(&g.level[u]) == l - 1) {
+        const int32_t want = (int32_t)((stamp << 16) | (uint32_t)(l - 1));
+        const int e = rp[y + 1];
+        for (int j = rp[y] + tid; j < e; j += T) {  // rows ascend: first hit per lane is its minimum
+            const int u = ci[j];
+            if ((unsigned)u < (unsigned)g.n && level[u] == want) {
                 atomicMin(&s_pred, u);
                 break;
             }
@@ -223,13 +263,15 @@ __device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path)
         if (y == INT_MAX) return 0;  // only with a non-symmetric CSR
         if (tid == 0) path[l - 1] = y;
     }
-    return L + 1;
+    return d + 1;
 }
 
 // Witness and certificate for one graph; all threads of the block call it.
 template <int T>
-__device__ void finish_graph(const GDesc &g, uint32_t flags)
+__device__ void finish_graph(const GDesc &g, uint32_t flags, uint64_t *lds)
 {
+    uint64_t *amask = lds, *vis = lds + g.wn, *nxt = lds + 2 * g.wn;
+    uint32_t stamp = 0;
     __shared__ uint32_t s_red[T / kWave];
     __shared__ uint32_t s_wcnt[T / kWave];
     const int tid = threadIdx.x;
@@ -279,9 +321,11 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags)
     }
     const int z = g.order[best];
 
+    for (int u = tid; u < g.n; u += T) g.level[u] = 0;  // stamp 0: never matches a search
+    block_sync_agent();
     int len = 0, fb = 0;
     if (!(flags & LEXBFS_FLAG_FORCE_FALLBACK)) {
-        len = bfs_path<T>(g, v, x, z, g.cycle + 1);
+        len = bfs_path<T>(g, v, x, z, g.cycle + 1, amask, vis, nxt, ++stamp);
         if (len > 0) {
             if (tid == 0) g.cycle[0] = v;
             len += 1;
@@ -318,7 +362,12 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags)
                 for (int ib = ia + 1; ib < k && len == 0; ++ib) {
                     const int b = g_load_i(&g.lnbuf[ib]);
                     if (test_bit(rowa, b)) continue;
-                    len = bfs_path<T>(g, v2, b, a, g.cycle + 1);
+                    if (stamp == 0xFFFFu) {  // stamps exhausted: clear the levels, start over
+                        for (int u = tid; u < g.n; u += T) g.level[u] = 0;
+                        block_sync_agent();
+                        stamp = 0;
+                    }
+                    len = bfs_path<T>(g, v2, b, a, g.cycle + 1, amask, vis, nxt, ++stamp);
                     if (len > 0) {
                         if (tid == 0) g.cycle[0] = v2;
                         len += 1;
@@ -343,15 +392,18 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags)
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-// State placement of a single-graph LexBFS launch.
-enum : int { kModeLdsRem = 0, kModeLds = 1, kModeGlobal = 2 };
+// State placement of a single-graph LexBFS launch, most capable first.
+enum : int { kModeLdsRem = 0, kModeLds = 1, kModeCompact = 2, kModeGlobal = 3 };
 
 template <int T, int kMode>
 __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
 {
     extern __shared__ uint64_t lds[];
     if (threadIdx.x == 0 && g.failkey) *g.failkey = kNoFail;
-    if (kMode == kModeGlobal) {
+    if (kMode == kModeCompact) {
+        BlockTeam<T, false> tm{(int)threadIdx.x};
+        lexbfs_team_compact(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_compact(lds, g.n, T));
+    } else if (kMode == kModeGlobal) {
         LdsLayoutG L = carve_lds_g(lds, g.n, T);
         GlobalTables tab{g.gtab, g.gtab + g.n};
         BlockTeam<T, true> tm{(int)threadIdx.x};
@@ -373,7 +425,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep_single(GDesc g, int row
 
 __global__ __launch_bounds__(kFinishThreads) void k_finish_single(GDesc g, uint32_t flags)
 {
-    finish_graph<kFinishThreads>(g, flags);
+    extern __shared__ uint64_t lds[];
+    finish_graph<kFinishThreads>(g, flags, lds);
 }
 
 // Batch: every block first takes large graphs (whole block per graph) from a
@@ -437,8 +490,9 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep_batch(const GDesc *__re
 
 __global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const GDesc *__restrict__ gds, uint32_t flags)
 {
+    extern __shared__ uint64_t lds[];
     const GDesc g = gds[blockIdx.x];
-    finish_graph<kFinishThreads>(g, flags);
+    finish_graph<kFinishThreads>(g, flags, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,8 +603,10 @@ int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
 {
     const size_t lim_r = dynamic_lds_limit(k_lexbfs_single<T, kModeLdsRem>);
     const size_t lim_l = dynamic_lds_limit(k_lexbfs_single<T, kModeLds>);
+    const size_t lim_c = dynamic_lds_limit(k_lexbfs_single<T, kModeCompact>);
     const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, kModeGlobal>);
-    if (!lim_r || !lim_l || !lim_g) return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
+    if (!lim_r || !lim_l || !lim_c || !lim_g)
+        return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
     const size_t b_r = lds_bytes_lds_tables(d.n, T, true);
     const size_t b_l = lds_bytes_lds_tables(d.n, T, false);
     const size_t b_g = lds_bytes_global_tables(d.n, T);
@@ -559,6 +615,8 @@ int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
         hipLaunchKernelGGL((k_lexbfs_single<T, kModeLdsRem>), dim3(1), dim3(T), b_r, s, d);
     } else if (b_l <= lim_l) {
         hipLaunchKernelGGL((k_lexbfs_single<T, kModeLds>), dim3(1), dim3(T), b_l, s, d);
+    } else if (lds_bytes_compact(d.n, T) <= lim_c) {
+        hipLaunchKernelGGL((k_lexbfs_single<T, kModeCompact>), dim3(1), dim3(T), lds_bytes_compact(d.n, T), s, d);
     } else {
         if (b_g > lim_g) return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
         hipLaunchKernelGGL((k_lexbfs_single<T, kModeGlobal>), dim3(1), dim3(T), b_g, s, d);
@@ -590,6 +648,9 @@ void sweep_shape(int wn, int &G, int &lg)
 
 // Rows per sweep block: every group of G lanes takes 4 rows.
 int sweep_rows_per_block(int G) { return (kSweepThreads / kWave) * (kWave / G) * 4; }
+
+// Dynamic LDS of the certificate kernel: three bitsets of wn words.
+size_t finish_lds(int wn) { return 3 * 8 * (size_t)(wn > 0 ? wn : 1); }
 
 GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *order, int32_t *rank,
                 int32_t *parent, int32_t *cycle, lexbfs_result_t *res)
@@ -666,6 +727,7 @@ struct lexbfs_batch_plan {
     size_t lds = 0;
     int region = 0;
     int blocks = 1;
+    size_t finish_lds = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -767,7 +829,7 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
     }
     {
         ProfScope ps(2, s);
-        hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), 0, s, d, flags);
+        hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), finish_lds(d.wn), s, d, flags);
     }
     LX_CHECK_LAUNCH("certificate launch");
     return LEXBFS_OK;
@@ -793,6 +855,13 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
         if (tuning->wave_max_n > 0) wave_max_n = tuning->wave_max_n;
     }
     wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
+    {
+        // Every wave of a workgroup needs its own region: keep the wave
+        // threshold where four regions fit the LDS of one workgroup.
+        const size_t lim = dynamic_lds_limit(k_lexbfs_batch<BT>);
+        while (wave_max_n > 64 && (size_t)(BT / kWave) * lds_bytes_lds_tables(wave_max_n, kWave, true) > lim)
+            wave_max_n -= 64;
+    }
     int maxn_block = 0, maxn_wave = 0;
     for (int i = 0; i < count; ++i) {
         const int rc = validate_graph(&gs[i]);
@@ -888,6 +957,9 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
     P->lds = lds;
     P->region = (int)region;
     P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
+    int maxwn = 1;
+    for (int i = 0; i < count; ++i) maxwn = std::max(maxwn, (gs[i].n + 63) / 64);
+    P->finish_lds = finish_lds(maxwn);
     const hipError_t e =
         hipMemcpyAsync(w + L.gds, P->table.data(), P->table.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e != hipSuccess) {
@@ -928,7 +1000,7 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
     }
     {
         ProfScope ps(2, s);
-        hipLaunchKernelGGL(k_finish_batch, dim3(P->count), dim3(kFinishThreads), 0, s, dg, P->flags);
+        hipLaunchKernelGGL(k_finish_batch, dim3(P->count), dim3(kFinishThreads), P->finish_lds, s, dg, P->flags);
     }
     LX_CHECK_LAUNCH("batch certificate launch");
     return LEXBFS_OK;

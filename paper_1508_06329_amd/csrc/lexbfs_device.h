@@ -513,6 +513,202 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
 }
 
 // ---------------------------------------------------------------------------
+// Compact LexBFS state for large n (4 bytes + 1/8 byte per vertex in LDS).
+// No class-end table: the last position of class c is the start of the next
+// live class above it minus one (or U - 1 for the top class), found in a
+// two-level bitmap of class starts (level 1 marks the non-zero words of
+// level 0). Split counters are 16 bits; the first neighbour of a class to
+// count itself leads it, and the classes are closed in a third phase after
+// a barrier (no "moved" counter, no rem).
+//   starts u64[wn] | sum u64[wn/64] | red u32[4 waves] | cls u16[n] | cnt u16[n]
+// ---------------------------------------------------------------------------
+__host__ __device__ inline size_t lds_bytes_compact(int n, int team)
+{
+    const size_t wn = (size_t)(n + 63) / 64;
+    const size_t ws = (wn + 63) / 64;
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    return align_up(8 * wn, 16) + align_up(8 * ws, 16) + align_up(16 * nred, 16) + 2 * align_up(2 * (size_t)n, 16);
+}
+
+struct CompactLayout {
+    uint64_t *starts;
+    uint64_t *sum;
+    uint32_t *red;
+    uint16_t *cls;
+    uint16_t *cnt;
+};
+
+__device__ __forceinline__ CompactLayout carve_compact(void *base, int n, int team)
+{
+    const size_t wn = (size_t)(n + 63) / 64;
+    const size_t ws = (wn + 63) / 64;
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    const size_t a = align_up(2 * (size_t)n, 16);
+    char *p = (char *)base;
+    CompactLayout L;
+    L.starts = (uint64_t *)p;
+    p += align_up(8 * wn, 16);
+    L.sum = (uint64_t *)p;
+    p += align_up(8 * ws, 16);
+    L.red = (uint32_t *)p;
+    p += align_up(16 * nred, 16);
+    L.cls = (uint16_t *)p;
+    L.cnt = (uint16_t *)(p + a);
+    return L;
+}
+
+// Start of the first live class above position c, or U if there is none.
+__device__ __forceinline__ uint32_t next_start(const uint64_t *starts, const uint64_t *sum, int nsum, uint32_t c,
+                                               uint32_t U)
+{
+    const uint32_t w = c >> 6;
+    const uint32_t b = c & 63u;
+    const uint64_t m = b == 63u ? 0ull : starts[w] & (~0ull << (b + 1u));
+    if (m) return min(U, (w << 6) + (uint32_t)ctz64(m));
+    const uint32_t w1 = w + 1u;
+    for (int s1 = (int)(w1 >> 6); s1 < nsum; ++s1) {
+        uint64_t mm = sum[s1];
+        if (s1 == (int)(w1 >> 6)) mm &= ~0ull << (w1 & 63u);
+        if (mm) {
+            const uint32_t ww = ((uint32_t)s1 << 6) + (uint32_t)ctz64(mm);
+            return min(U, (ww << 6) + (uint32_t)ctz64(starts[ww]));
+        }
+    }
+    return U;
+}
+
+template <class Team>
+__device__ void lexbfs_team_compact(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_,
+                                    int32_t *rank_, int32_t *parent_, const CompactLayout &L)
+{
+    LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
+    LX_GLOBAL int32_t *__restrict__ order = as_global(order_);
+    LX_GLOBAL int32_t *__restrict__ rank = as_global(rank_);
+    LX_GLOBAL int32_t *__restrict__ parent = as_global(parent_);
+    constexpr int T = Team::kSize;
+    constexpr int NW = Team::kWaves;
+    uint64_t *starts = L.starts, *sum = L.sum;
+    uint16_t *cls = L.cls, *cnt = L.cnt;
+    uint32_t *red = L.red;
+    const int t = tm.tid;
+    if (n <= 0) return;
+    const int wn = (n + 63) >> 6;
+    const int nsum = (wn + 63) >> 6;
+    int K = 1;
+    while (K * T < n) K <<= 1;
+    const int vbase = t * K;
+    const int wi = vbase >> 6;
+    const int sh = vbase & 63;
+    const uint32_t wbase = (uint32_t)wi << 6;
+    uint64_t cmask = (K == 64) ? ~0ull : (((1ull << K) - 1ull) << sh);
+    if (wi == wn - 1 && (n & 63)) cmask &= (1ull << (n & 63)) - 1ull;
+    const bool owner = vbase < n;
+    LX_GLOBAL const uint64_t *rowbase = bits + wi;
+    auto cnt_inc = [&](uint32_t c) -> uint32_t {
+        const uint32_t s = (c & 1u) * 16u;
+        return (atomicAdd((uint32_t *)cnt + (c >> 1), 1u << s) >> s) & 0xFFFFu;
+    };
+
+    for (int v = t; v < n; v += T) {
+        cls[v] = 0;
+        cnt[v] = 0;
+    }
+    for (int w = t; w < wn; w += T) starts[w] = w == 0 ? 1ull : 0ull;
+    for (int w = t; w < nsum; w += T) sum[w] = w == 0 ? 1ull : 0ull;
+    if (owner)
+        for (int v = vbase; v < min(vbase + K, n); ++v) parent[v] = -1;
+    tm.sync();
+
+    uint64_t um = owner ? cmask : 0ull;
+    uint64_t top = um;
+    uint32_t x = 0;
+    uint64_t rw = owner ? rowbase[0] : 0ull;
+    int par = 0;
+    int U = n;
+    for (int i = 0; i < n; ++i) {
+        U -= 1;
+        const uint32_t stop = cls[x];
+        if (owner && (x >> 6) == (uint32_t)wi) {
+            um &= ~(1ull << (x & 63));
+            top &= ~(1ull << (x & 63));
+        }
+        uint64_t nb = rw & um;
+        __asm__ volatile("" : "+v"(nb)::"memory");
+        if (t == 0) {
+            if ((int)stop >= U) {  // the top class is gone
+                const uint64_t left =
+                    atomicAnd((unsigned long long *)&starts[stop >> 6], ~(1ull << (stop & 63))) & ~(1ull << (stop & 63));
+                if (!left) atomicAnd((unsigned long long *)&sum[stop >> 12], ~(1ull << ((stop >> 6) & 63)));
+            }
+            order[i] = (int32_t)x;
+            rank[x] = i;
+        }
+        // Phase A: count neighbours per class; the first one leads the class.
+        uint64_t lead = 0;
+        for (uint64_t m = nb; m; m &= m - 1) {
+            const int b = ctz64(m);
+            const int y = (int)wbase + b;
+            const uint32_t C = cls[y];
+            parent[y] = (int32_t)x;
+            if (cnt_inc(C) == 0) lead |= 1ull << b;
+        }
+        if (i + 1 == n) break;
+        uint32_t k = tm.max_all(pick_key(top, nb, wbase), red + par * 2 * NW);
+        par ^= 1;
+        if ((k >> 16) == 0) {
+            uint32_t hi = 0;
+            for (int w = t; w < wn; w += T) {
+                const uint64_t sw = starts[w];
+                if (sw) hi = max(hi, (uint32_t)((w << 6) | (63 - __builtin_clzll(sw))) + 1u);
+            }
+            const uint32_t c1 = tm.max_all(hi, red + par * 2 * NW) - 1u;
+            par ^= 1;
+            top = chunk_match(cls, um, c1, vbase, sh, K);
+            k = tm.max_all(pick_key(top, nb, wbase), red + par * 2 * NW);
+            par ^= 1;
+        }
+        const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
+        if ((k >> 16) == 2) top &= nb;
+        const uint64_t rwn = owner ? rowbase[(int64_t)xn * W] : 0ull;
+
+        // Phase B: move the neighbours up; leaders remember the old class.
+        uint64_t split = 0;
+        for (uint64_t m = nb; m; m &= m - 1) {
+            const int b = ctz64(m);
+            const int y = (int)wbase + b;
+            const uint32_t C = cls[y];
+            const uint32_t c = cnt[C];
+            const uint32_t last = next_start(starts, sum, nsum, C, (uint32_t)U) - 1u;
+            if (c < last - C + 1) {
+                const uint32_t nw = last + 1 - c;
+                cls[y] = (uint16_t)nw;
+                if ((lead >> b) & 1ull) {
+                    cnt[nw] = (uint16_t)C;
+                    split |= 1ull << b;
+                }
+            }
+        }
+        tm.sync();
+        // Phase C: leaders close their classes and publish the new starts.
+        for (uint64_t m = lead; m; m &= m - 1) {
+            const int b = ctz64(m);
+            const uint32_t nw = cls[(int)wbase + b];
+            if ((split >> b) & 1ull) {
+                cnt[cnt[nw]] = 0;
+                cnt[nw] = 0;
+                atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
+                atomicOr((unsigned long long *)&sum[nw >> 12], 1ull << ((nw >> 6) & 63));
+            } else {
+                cnt[nw] = 0;
+            }
+        }
+        tm.sync();
+        x = xn;
+        rw = rwn;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Perfect-elimination sweep (Section 6.2 "testing"): v fails iff some
 // z in LN(v) \ {p(v)} is not adjacent to p(v). Every such z lies before
 // p(v) in the order, and every neighbour of v before p(v) is in LN(v), so

@@ -1,0 +1,290 @@
+"""Serving: continuous batching of chordality requests on one GPU.
+
+Requests (graphs of mixed sizes) arrive over time. The server admits a
+request when its device footprint (bitset + CSR + per-graph workspace) fits
+the remaining memory budget and an in-flight slot is free, uploads it on a
+copy stream, and folds every uploaded request that is not yet running into
+the next batch launch. Launches go round-robin over several compute
+streams, so a batch formed while earlier ones still run overlaps them on the
+device. When a launch completes, its requests record their latency
+(completion - arrival) and release their memory, which admits more.
+
+Graphs above the batch kernel's size limit run as single-graph calls on the
+same streams. Every result is a pure function of its own graph, so a request
+gets the same verdict, witness and certificate alone or in any mix.
+
+The admission logic (:class:`AdmissionController`) is plain host code with no
+device dependency; the tests drive it with a fake clock and executor.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Deque, Dict, List, Optional, Sequence
+
+# Largest n the batch kernel runs (64 vertices per lane, 256-lane teams).
+BATCH_MAX_N = 64 * 256
+
+
+def footprint_bytes(n: int, nnz: int, W: Optional[int] = None) -> int:
+    """Device bytes one request holds while admitted: the bitset, the CSR,
+    its result record and its share of the workspace (about ten int32
+    arrays of n entries, 256-byte aligned)."""
+    W = (n + 63) // 64 if W is None else W
+    al = lambda x: (x + 255) // 256 * 256
+    return al(8 * max(n * W, 1)) + al(4 * (n + 1)) + al(4 * max(nnz, 1)) + 10 * al(4 * max(n, 1)) + 1024
+
+
+@dataclass
+class Request:
+    rid: int
+    graph: object                 # host graph (graphgen.Graph-like)
+    arrival: float                # seconds, on the server's clock
+    nbytes: int = 0
+    admitted: float = -1.0
+    done: float = -1.0
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class AdmissionController:
+    """FIFO admission under a byte budget and a slot limit.
+
+    A request larger than the whole budget can never be admitted; it is
+    rejected (``rejected``) instead of blocking the queue."""
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 1 << 30):
+        self.budget = int(budget_bytes)
+        self.max_inflight = int(max_inflight)
+        self.used = 0
+        self.inflight = 0
+        self.queue: Deque[Request] = collections.deque()
+        self.rejected: List[Request] = []
+        self.peak_used = 0
+
+    def submit(self, r: Request):
+        if r.nbytes > self.budget:
+            self.rejected.append(r)
+        else:
+            self.queue.append(r)
+
+    def admit(self, now: float) -> List[Request]:
+        """Admit from the head of the queue while the head fits."""
+        out = []
+        while self.queue and self.inflight < self.max_inflight and self.used + self.queue[0].nbytes <= self.budget:
+            r = self.queue.popleft()
+            self.used += r.nbytes
+            self.inflight += 1
+            r.admitted = now
+            out.append(r)
+        self.peak_used = max(self.peak_used, self.used)
+        return out
+
+    def release(self, r: Request):
+        self.used -= r.nbytes
+        self.inflight -= 1
+        assert self.used >= 0 and self.inflight >= 0
+
+
+def run_loop(requests: Sequence[Request], ctrl: AdmissionController, executor, clock: Callable[[], float],
+             idle: Callable[[], None], max_launches: int = 3):
+    """Drive arrivals, admission, launches and completions until every
+    request is done or rejected. At most `max_launches` launches run at
+    once (one per compute stream); requests arriving meanwhile queue and
+    are admitted together into the next launch. `executor` provides
+    ``start(requests) -> handle`` (upload + launch, asynchronous),
+    ``ready(handle) -> bool`` and ``finish(handle)`` (collect results).
+    Returns the requests in completion order."""
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    running = []
+    finished = []
+    total = len(requests)
+    while len(finished) + len(ctrl.rejected) < total:
+        now = clock()
+        while pending and pending[0].arrival <= now:
+            ctrl.submit(pending.popleft())
+        adm = ctrl.admit(now) if len(running) < max_launches else []
+        if adm:
+            running.append((executor.start(adm), adm))
+        progressed = bool(adm)
+        still = []
+        for h, rs in running:
+            if executor.ready(h):
+                executor.finish(h)
+                t = clock()
+                for r in rs:
+                    r.done = t
+                    ctrl.release(r)
+                    finished.append(r)
+                progressed = True
+            else:
+                still.append((h, rs))
+        running = still
+        if not progressed:
+            idle()
+    return finished
+
+
+def percentile(xs: Sequence[float], q: float) -> float:
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+class GpuExecutor:
+    """Uploads admitted graphs on a copy stream and launches them, as one
+    prepared batch plus single-graph calls for graphs above the batch
+    limit, on the next of several compute streams."""
+
+    def __init__(self, device="cuda", streams: int = 3, outputs: bool = False):
+        import torch
+
+        from . import _lib
+
+        self.torch = torch
+        self.lib = _lib.load()
+        self.dev = torch.device(device)
+        self.copy = torch.cuda.Stream(device=self.dev)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
+        self.next = 0
+        self.outputs = outputs
+
+    def _upload(self, graphs):
+        from . import DeviceGraph
+
+        torch = self.torch
+        out = []
+        with torch.cuda.stream(self.copy):
+            for g in graphs:
+                rp = torch.from_numpy(g.row_ptr).pin_memory().to(self.dev, non_blocking=True)
+                ci_h = g.col_idx if g.col_idx.size else g.col_idx.reshape(0)
+                ci = torch.from_numpy(ci_h).pin_memory().to(self.dev, non_blocking=True)
+                bits = torch.from_numpy(g.bits.view("int64")).pin_memory().to(self.dev, non_blocking=True)
+                out.append(DeviceGraph(g.n, g.W, rp, ci, bits))
+        ev = torch.cuda.Event()
+        ev.record(self.copy)
+        return out, ev
+
+    def start(self, reqs: Sequence[Request]):
+        from . import BatchPlan, _lib, lexbfs_outputs_t
+
+        torch = self.torch
+        s = self.streams[self.next]
+        self.next = (self.next + 1) % len(self.streams)
+        dgs, up = self._upload([r.graph for r in reqs])
+        s.wait_event(up)
+        small = [i for i, g in enumerate(dgs) if g.n <= BATCH_MAX_N]
+        large = [i for i, g in enumerate(dgs) if g.n > BATCH_MAX_N]
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "small": small, "large": []}
+        with torch.cuda.stream(s):
+            if small:
+                plan = BatchPlan([dgs[i] for i in small], outputs=self.outputs, stream=s)
+                plan.launch(stream=s)
+                handle["plan"] = plan
+            for i in large:
+                g = dgs[i]
+                res = torch.zeros(8, dtype=torch.int32, device=self.dev)
+                outs = lexbfs_outputs_t()
+                tens = {}
+                if self.outputs:
+                    for k in ("order", "rank", "parent", "cycle"):
+                        tens[k] = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.dev)
+                        setattr(outs, k, tens[k].data_ptr())
+                ws = torch.empty(self.lib.lexbfs_workspace_bytes(g.n), dtype=torch.uint8, device=self.dev)
+                d = g.desc()
+                rc = self.lib.chordal_test(ctypes.byref(d), res.data_ptr(), ctypes.byref(outs), ws.data_ptr(),
+                                           ws.numel(), 0, s.cuda_stream)
+                _lib.check(rc, "chordal_test")
+                handle["large"].append((i, res, ws, tens))
+        ev = torch.cuda.Event()
+        ev.record(s)
+        handle["event"] = ev
+        return handle
+
+    def ready(self, handle) -> bool:
+        return handle["event"].query()
+
+    def finish(self, handle):
+        from . import Result, _result_from
+
+        reqs = handle["reqs"]
+        if handle["plan"] is not None:
+            rs = handle["plan"].results()
+            for j, i in enumerate(handle["small"]):
+                reqs[i].result = rs[j]
+            handle["plan"].close()
+        for i, res, ws, tens in handle["large"]:
+            chordal, wit, clen, fb = _result_from(res.cpu())
+            n = handle["dgs"][i].n
+            reqs[i].result = Result(chordal, wit, clen, fb, **{k: v[:n] for k, v in tens.items()})
+        handle["dgs"] = None
+
+
+class SerialExecutor(GpuExecutor):
+    """The plain per-graph path: one request at a time, one chordal_test per
+    request, on one stream (admission limited to one in flight)."""
+
+    def __init__(self, device="cuda", outputs: bool = False):
+        super().__init__(device, streams=1, outputs=outputs)
+
+    def start(self, reqs: Sequence[Request]):
+        from . import _lib, lexbfs_outputs_t
+
+        torch = self.torch
+        s = self.streams[0]
+        dgs, up = self._upload([r.graph for r in reqs])
+        s.wait_event(up)
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "small": [], "large": []}
+        for i, g in enumerate(dgs):
+            res = torch.zeros(8, dtype=torch.int32, device=self.dev)
+            outs = lexbfs_outputs_t()
+            tens = {}
+            if self.outputs:
+                for k in ("order", "rank", "parent", "cycle"):
+                    tens[k] = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.dev)
+                    setattr(outs, k, tens[k].data_ptr())
+            ws = torch.empty(self.lib.lexbfs_workspace_bytes(g.n), dtype=torch.uint8, device=self.dev)
+            d = g.desc()
+            rc = self.lib.chordal_test(ctypes.byref(d), res.data_ptr(), ctypes.byref(outs), ws.data_ptr(),
+                                       ws.numel(), 0, s.cuda_stream)
+            _lib.check(rc, "chordal_test")
+            handle["large"].append((i, res, ws, tens))
+        ev = torch.cuda.Event()
+        ev.record(s)
+        handle["event"] = ev
+        return handle
+
+
+def serve(graphs: Sequence, arrivals: Sequence[float], budget_bytes: int = 64 << 30, serial: bool = False,
+          outputs: bool = False, max_inflight: int = 1 << 30, device="cuda") -> Dict:
+    """Run a request stream (graphs[i] arrives at arrivals[i] seconds after
+    the start) through the continuous-batching server (or, with
+    serial=True, through the plain per-graph path). Returns the requests
+    and summary statistics."""
+    ex = SerialExecutor(device, outputs) if serial else GpuExecutor(device, outputs=outputs)
+    ctrl = AdmissionController(budget_bytes, 1 if serial else max_inflight)
+    reqs = [Request(i, g, float(a), footprint_bytes(g.n, g.nnz, g.W)) for i, (g, a) in enumerate(zip(graphs, arrivals))]
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0
+    done = run_loop(reqs, ctrl, ex, clock, idle=lambda: time.sleep(20e-6), max_launches=1 if serial else len(ex.streams))
+    wall = clock()
+    lat = [r.latency for r in done]
+    span = max(r.done for r in done) - min(r.arrival for r in done) if done else float("nan")
+    return {
+        "requests": reqs,
+        "completed": len(done),
+        "rejected": len(ctrl.rejected),
+        "wall_s": wall,
+        "throughput": len(done) / span if span > 0 else float("nan"),
+        "p50_ms": percentile(lat, 50) * 1e3,
+        "p99_ms": percentile(lat, 99) * 1e3,
+        "peak_bytes": ctrl.peak_used,
+    }

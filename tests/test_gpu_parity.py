@@ -194,3 +194,20 @@ def test_batch_workload_full():
             bad.append(i)
     assert bad == []
     assert sum(r.chordal for r in rs) == 2048
+
+
+# ---------------------------------------------------------------------------
+# Sizes whose LexBFS state only fits LDS in the compact layout
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["gnp25000", "subtree32768_planted", "split30000", "edgeless20000"])
+def test_compact_mode_sizes(case):
+    if case == "gnp25000":
+        g = gg.gnp(25000, 0.0004, 21)
+    elif case == "subtree32768_planted":
+        g = gg.plant(gg.subtree(32760, 8000, 12, 22), 8, 23)
+    elif case == "split30000":
+        g = gg.split_pair(1000, 29000, 12, 24)[1]
+    else:
+        g = gg.from_edges(20000, [])
+    check_single(g, tag="compact")
