@@ -139,6 +139,16 @@ def percentile(xs: Sequence[float], q: float) -> float:
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def pin_graph(g):
+    """Page-locked host copies (row_ptr, col_idx, bits) of a host graph, so
+    its upload is a plain asynchronous DMA."""
+    import torch
+
+    ci = g.col_idx if g.col_idx.size else g.col_idx.reshape(0)
+    return (torch.from_numpy(g.row_ptr).pin_memory(), torch.from_numpy(ci).pin_memory(),
+            torch.from_numpy(g.bits.view("int64")).pin_memory())
+
+
 class GpuExecutor:
     """Uploads admitted graphs on a copy stream and launches them, as one
     prepared batch plus single-graph calls for graphs above the batch
@@ -164,10 +174,8 @@ class GpuExecutor:
         out = []
         with torch.cuda.stream(self.copy):
             for g in graphs:
-                rp = torch.from_numpy(g.row_ptr).pin_memory().to(self.dev, non_blocking=True)
-                ci_h = g.col_idx if g.col_idx.size else g.col_idx.reshape(0)
-                ci = torch.from_numpy(ci_h).pin_memory().to(self.dev, non_blocking=True)
-                bits = torch.from_numpy(g.bits.view("int64")).pin_memory().to(self.dev, non_blocking=True)
+                hp = getattr(g, "pinned", None) or pin_graph(g)
+                rp, ci, bits = (t.to(self.dev, non_blocking=True) for t in hp)
                 out.append(DeviceGraph(g.n, g.W, rp, ci, bits))
         ev = torch.cuda.Event()
         ev.record(self.copy)
