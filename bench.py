@@ -7,13 +7,14 @@ G(n, p) with average degree 8, 25% subtree graphs with a planted chordless
 cycle of length 4..12 -- seed 0, synthetic, resident in HBM before timing.
 
 A step is one pass of the whole path over the batch: one prepared
-lexbfs_batch_plan_launch (LexBFS for every graph, the perfect-elimination
-sweep, witnesses and certificates). `value` is whole-job tests/s over the K
+lexbfs_batch_plan_launch (for every graph, on one team: LexBFS with the
+perfect-elimination test folded into its steps, then the witness and
+certificate). `value` is whole-job tests/s over the K
 timed steps. The per-graph path (one chordal_test call per graph) is timed
 on an evenly spaced sample of the same graphs, and the CPU oracle on a
 bounded sample on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch|single-small|single-large|split]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch|single-small|single-large|split|serving|copy]
 """
 import argparse
 import json
@@ -37,12 +38,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "single-small", "single-large", "split", "serving"])
+                    choices=["batch", "single-small", "single-large", "split", "serving", "copy"])
     ap.add_argument("--serving-pool", type=int, default=192)
     ap.add_argument("--serving-requests", type=int, default=800)
     ap.add_argument("--per-graph-sample", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     return ap.parse_args()
 
 
@@ -52,21 +54,39 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
 
 
-def algorithmic_bytes(graphs):
+def components(g):
+    import numpy as np
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    if g.n == 0:
+        return 0
+    a = csr_matrix((np.ones(len(g.col_idx), dtype=np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    return int(connected_components(a, directed=False)[0])
+
+
+def algorithmic_bytes(graphs, fused=False):
     """Per pass: the bitset read once (n rows of ceil(n/64) words) and the
-    int32 per-vertex arrays each kernel touches."""
-    bitset = sum(g.n * 8 * ((g.n + 63) // 64) for g in graphs)
+    int32 per-vertex arrays each kernel touches. With the elimination test
+    fused into LexBFS (the batch kernel) that kernel also reads the parent's
+    row of every vertex that has a parent (all but the first vertex of each
+    connected component)."""
+    row = lambda g: 8 * ((g.n + 63) // 64)
+    bitset = sum(g.n * row(g) for g in graphs)
     sn = sum(g.n for g in graphs)
-    return {"lexbfs": bitset + 12 * sn,  # pivot rows; order, rank, parent written
-            "sweep": bitset + 8 * sn,    # every row once; rank and parent read
-            "certificate": 0, "setup": 0}
+    out = {"lexbfs": bitset + 12 * sn,  # pivot rows; order, rank, parent written
+           "sweep": bitset + 8 * sn,    # every row once; rank and parent read
+           "certificate": 0, "setup": 0}
+    if fused:
+        out["lexbfs"] += sum((g.n - components(g)) * row(g) for g in graphs)
+    return out
 
 
-def roofline_from(timing, steps, graphs):
+def roofline_from(timing, steps, graphs, fused=False):
     """Algorithmic bytes of one pass split evenly over the launches of one
     pass (a batch pass launches each kernel once; the single-graph workloads
     launch each kernel once per graph, and their graphs have equal n)."""
-    ab = algorithmic_bytes(graphs)
+    ab = algorithmic_bytes(graphs, fused)
     per_kind = {}
     for kind, (count, ms) in timing.items():
         if count == 0:
@@ -81,6 +101,92 @@ def roofline_from(timing, steps, graphs):
             "frac": (d["gbs"] / HBM_PEAK_GBS) if d["gbs"] is not None else None, "traffic": None,
             "kernel": dom, "avg_launch_ms": d["avg_ms"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
     return roof, per_kind
+
+
+KERNEL_SOURCES = ("paper_1508_06329_amd/csrc/lexbfs.hip", "paper_1508_06329_amd/csrc/lexbfs_device.h")
+
+
+def kernel_source_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_sha()
+    for line in open(path):
+        if line.startswith("traffic:"):
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("source_sha256") == want:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
+def bench_copy(args):
+    """A plain device copy of known size (int32 negation, out of place):
+    the calibration kernel for the HBM byte counters."""
+    import torch
+
+    nbytes = 512 << 20
+    x = torch.arange(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(max(args.warmup, 1)):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert int(y[12345].item()) == -12345
+    print(json.dumps({"workload": "copy: int32 negation, 512 MiB read + 512 MiB written per launch",
+                      "read_bytes": nbytes, "write_bytes": nbytes, "launches": args.steps,
+                      "gbs": 2 * nbytes * args.steps / el / 1e9}), flush=True)
+
+
+def cpu_oracle_rate(graphs, seconds, threads):
+    """The oracle (unchanged) over the workload's graphs in generation order
+    on `threads` host threads (ctypes releases the GIL), for about `seconds`
+    or 64 passes, whichever ends first."""
+    import itertools
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle.chordal_test(graphs[0])
+    counter = itertools.count()
+    lock = threading.Lock()
+    stats = {"done": 0, "edges": 0}
+    limit = 64 * len(graphs)
+    t0 = time.perf_counter()
+
+    def worker():
+        while time.perf_counter() - t0 < seconds:
+            k = next(counter)
+            if k >= limit:
+                break
+            g = graphs[k % len(graphs)]
+            oracle.chordal_test(g)
+            with lock:
+                stats["done"] += 1
+                stats["edges"] += g.m
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for f in [ex.submit(worker) for _ in range(threads)]:
+            f.result()
+    el = time.perf_counter() - t0
+    return stats["done"], stats["edges"], el
 
 
 def main():
@@ -101,6 +207,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     t = time.time()
     if args.workload == "batch":
         graphs = gg.config_batch()
@@ -124,8 +232,13 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---------------- batched path ----------------
+    tune = None
     if args.workload == "batch":
-        plan = lx.BatchPlan(dgs)
+        from paper_1508_06329_amd import autotune
+
+        tune = autotune.autotune_batch(dgs, reps=2)
+        log(f"autotuned schedule {tune['tuning']} from {tune['ms']}")
+        plan = lx.BatchPlan(dgs, tuning=tune["tuning"])
 
         def step():
             plan.launch()
@@ -160,11 +273,26 @@ def main():
     step_ms = [a.elapsed_time(b) for a, b in evs]
     value = len(graphs) * args.steps / elapsed
     log(f"timed {args.steps} steps in {elapsed:.3f}s -> {value:.1f} tests/s")
-    roof, per_kind = roofline_from(timing, args.steps, graphs)
+    roof, per_kind = roofline_from(timing, args.steps, graphs, fused=args.workload == "batch")
+    roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+
+    # ---------------- the same pass as a replayed HIP graph ----------------
+    hipgraph = None
+    if args.workload == "batch":
+        graph = plan.capture()
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        g_el = time.perf_counter() - t0
+        hipgraph = {"ms_per_step": g_el / args.steps * 1e3, "tests_per_s": len(graphs) * args.steps / g_el}
+        log(f"hip graph replay: {hipgraph['tests_per_s']:.1f} tests/s")
 
     # ---------------- per-graph path ----------------
     per_graph = None
-    if args.workload == "batch":
+    if args.workload == "batch" and args.per_graph_sample > 0:
         idx = np.linspace(0, len(dgs) - 1, min(args.per_graph_sample, len(dgs))).astype(int)
         sample = [dgs[i] for i in idx]
         maxn = max(g.n for g in sample)
@@ -204,24 +332,17 @@ def main():
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-
-        done, t0 = 0, time.perf_counter()
-        edges = 0
-        order = list(range(len(graphs)))
-        while True:
-            g = graphs[order[done % len(graphs)]]
-            oracle.chordal_test(g)
-            edges += g.m
-            done += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds or done >= 4 * len(graphs):
-                break
-        cpu_el = time.perf_counter() - t0
-        cpu = {"value": done / cpu_el, "unit": "tests/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} graphs of the same workload in generation order ({cpu_el:.1f}s, one thread: "
-                         f"partition-refinement LexBFS + parent test + certificate)",
-               "edges_per_s": edges / cpu_el}
-        log(f"cpu oracle: {cpu['value']:.1f} tests/s")
+        rows = {}
+        for threads in sorted({1, args.cpu_threads}):
+            done, edges, cpu_el = cpu_oracle_rate(graphs, args.cpu_seconds, threads)
+            rows[threads] = {"value": done / cpu_el, "unit": "tests/s", "cores": threads, "kind": "oracle",
+                             "sample": f"{done} graphs of the same workload in generation order ({cpu_el:.1f}s on "
+                                       f"{threads} thread(s): partition-refinement LexBFS + parent test + "
+                                       f"certificate, one graph per thread at a time)",
+                             "edges_per_s": edges / cpu_el}
+            log(f"cpu oracle on {threads} thread(s): {rows[threads]['value']:.1f} tests/s")
+        cpu = dict(rows[max(rows)])
+        cpu["one_core"] = {k: rows[1][k] for k in ("value", "edges_per_s", "sample")}
 
     out = {
         "metric": "chordality tests/s and edges/s, batched vs per-graph on 1 MI355X; p50/p99 ms",
@@ -243,6 +364,8 @@ def main():
         "roofline": roof,
         "kernels": per_kind,
         "per_graph": per_graph,
+        "schedule": tune,
+        "hipgraph": hipgraph,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -58,6 +58,11 @@ extern "C" {
 
 /* Flags for chordal_test / chordal_test_batch. */
 #define LEXBFS_FLAG_FORCE_FALLBACK 0x1u /* build the certificate with the fallback rule only (test hook) */
+/* chordal_test only: run LexBFS as one round of three launches per step
+ * (the host loop of Section 6.1, one thread per vertex, tables in global
+ * memory) instead of the persistent kernel. Same results; a comparison form,
+ * slower by the per-launch cost times 3n. Ignored by chordal_test_batch. */
+#define LEXBFS_FLAG_PER_STEP 0x2u
 
 /* One graph. All pointers are device memory. */
 typedef struct lexbfs_graph {
@@ -134,11 +139,14 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
 
 /* Schedule for chordal_test_batch. A graph with n <= wave_max_n is run by
  * one 64-lane wavefront; a larger one by a whole workgroup of
- * block_threads lanes. lds_bytes is the dynamic LDS per workgroup
- * (0 = derived from the largest graph). */
+ * block_threads lanes. wave_max_n = 0 takes the built-in threshold (1024),
+ * a negative value puts every graph on a workgroup; the threshold is
+ * lowered, in steps of 64, until four wavefront states fit the LDS of one
+ * workgroup. lds_bytes is the dynamic LDS per workgroup (0 = derived from
+ * the largest graph). */
 typedef struct lexbfs_tuning {
     int32_t wave_max_n;
-    int32_t block_threads;   /* 256 or 1024 */
+    int32_t block_threads;   /* 0 or 256 (the workgroup size); others: LEXBFS_EINVAL */
     int32_t lds_bytes;
     int32_t reserved;
 } lexbfs_tuning_t;
@@ -158,8 +166,11 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count);
  * Equivalent to lexbfs_batch_plan_create + lexbfs_batch_plan_launch +
  * lexbfs_batch_plan_destroy: the per-graph descriptor table is staged into
  * the workspace with a host-to-device copy on `stream`; the calling thread
- * returns once the table has been staged. Every graph needs n <= LEXBFS_MAX_N and must fit
- * the workgroup's LDS (n <= 16384 with the built-in schedule).
+ * returns once the table has been staged. Every graph needs
+ * n <= lexbfs_batch_max_n() (its state must fit one workgroup's LDS).
+ * Each graph runs start to finish on one team (a wavefront or a workgroup):
+ * LexBFS with the perfect-elimination test of Section 5.2 folded into its
+ * steps, then the witness and certificate, so results match chordal_test.
  * Errors: as chordal_test; LEXBFS_ETOOBIG names a graph beyond the limit.
  */
 int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
@@ -205,6 +216,11 @@ const char *lexbfs_last_error(void);
 #define LEXBFS_KERNEL_KINDS 4 /* 0 LexBFS, 1 elimination sweep, 2 witness and certificate, 3 batch setup */
 int lexbfs_profile_enable(int on);
 int lexbfs_profile_collect(int32_t *counts, double *ms);
+
+/* Largest n a graph of chordal_test_batch (and of a batch plan) may have on
+ * the current device: the team's state must fit one workgroup's LDS
+ * (about 12 bytes per vertex). Negative LEXBFS_E* code on a HIP failure. */
+int32_t lexbfs_batch_max_n(void);
 
 /* Library ABI version (incremented on incompatible changes). */
 int lexbfs_abi_version(void);

@@ -15,11 +15,12 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_MAX_N, LexbfsError, lexbfs_graph_t, lexbfs_outputs_t,
+from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_PER_STEP, LEXBFS_MAX_N, LexbfsError, lexbfs_graph_t, lexbfs_outputs_t,
                    lexbfs_result_t, lexbfs_tuning_t)
 
 __all__ = ["BatchPlan", "pack_graphs", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
-           "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK"]
+           "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK",
+           "LEXBFS_FLAG_PER_STEP"]
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -299,6 +300,22 @@ class BatchPlan:
     def launch(self, stream=None):
         rc = _lib.load().lexbfs_batch_plan_launch(self.handle, _stream_handle(stream))
         _lib.check(rc, "lexbfs_batch_plan_launch")
+
+    def capture(self, stream=None) -> "torch.cuda.CUDAGraph":
+        """Record one launch of this plan into a HIP graph (kernel nodes only:
+        the launch issues no memset or copy). Replaying the graph is the same
+        launch; results are read as after launch(). Capturing turns the
+        library's kernel timing (KernelTimer) off: its events are host-side
+        bookkeeping that a replay would not update."""
+        if _lib.load().lexbfs_profile_enable(0) != 0:
+            raise LexbfsError(-1, "disabling kernel timing before capture")
+        stream = stream or torch.cuda.Stream(device=self.res.device)
+        stream.wait_stream(torch.cuda.current_stream(self.res.device))
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            self.launch()
+        torch.cuda.current_stream(self.res.device).wait_stream(stream)
+        return graph
 
     def results(self) -> List[Result]:
         host = self.res.cpu()

@@ -111,23 +111,9 @@ struct GDesc {
     lexbfs_result_t *res;
 };
 
-struct SweepItem {
-    int32_t g;
-    int32_t r0;
-    int32_t r1;
-    int32_t pad;
-};
-
 // ---------------------------------------------------------------------------
-// Block helpers
+// Helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_sync_agent()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
 __device__ __forceinline__ int32_t cas_agent(int32_t *p, int32_t expected, int32_t desired)
 {
     __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -139,18 +125,30 @@ __device__ __forceinline__ bool test_bit(const uint64_t *row, int u) { return (r
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
-// Block-wide min; every thread gets the result. s: LDS scratch of T/64 words.
-template <int T>
-__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t *s)
+// LDS of the certificate search of one team: a few shared integers, then
+// three bitsets of wn words.
+//   sc[0] frontier size, sc[1] predecessor, sc[2 .. 2+NW) reduction words,
+//   sc[2+NW .. 2+2NW) per-wave counts
+struct FinishLds {
+    int32_t *sc;
+    uint64_t *amask, *vis, *nxt;
+};
+
+__host__ __device__ inline size_t finish_head_bytes(int nwaves) { return align_up(4 * (2 + 2 * (size_t)nwaves), 16); }
+
+__host__ __device__ inline size_t finish_lds_bytes(int wn, int nwaves)
 {
-    v = wave_min_u32(v);
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint32_t r = s[0];
-#pragma unroll
-    for (int k = 1; k < T / kWave; ++k) r = min(r, s[k]);
-    __syncthreads();
-    return r;
+    return finish_head_bytes(nwaves) + 3 * 8 * (size_t)(wn > 0 ? wn : 1);
+}
+
+__device__ __forceinline__ FinishLds carve_finish(void *base, int wn, int nwaves)
+{
+    FinishLds F;
+    F.sc = (int32_t *)base;
+    F.amask = (uint64_t *)((char *)base + finish_head_bytes(nwaves));
+    F.vis = F.amask + (wn > 0 ? wn : 1);
+    F.nxt = F.vis + (wn > 0 ? wn : 1);
+    return F;
 }
 
 // ---------------------------------------------------------------------------
@@ -158,29 +156,29 @@ __device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t *s)
 // stopped after the layer that reaches dst; then back from dst, taking the
 // smallest-id neighbour of the previous layer each time. Writes
 // path[0] = src .. path[d] = dst and returns d + 1, or 0 if unreachable.
-// All threads of the block call it with the same arguments.
+// Every lane of the team calls it with the same arguments.
 //
 // Layers are bitsets: a layer's successor is the OR of its vertices' rows,
-// masked by A and by the visited set. The block's waves split the frontier
+// masked by A and by the visited set. The team's waves split the frontier
 // (four rows in flight per wave), lanes split the words of a row, and the
 // partial layers meet in LDS through atomic ORs. Each newly reached vertex
 // gets level[u] = stamp << 16 | depth; stamps keep successive searches of
 // one call apart without clearing level[] between them.
-// LDS: amask, vis, nxt -- three bitsets of wn words each.
 // ---------------------------------------------------------------------------
-template <int T>
-__device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path, uint64_t *amask, uint64_t *vis,
-                        uint64_t *nxt, uint32_t stamp)
+template <class Team>
+__device__ int bfs_path(const Team &tm, const GDesc &g, int c, int src, int dst, int32_t *path, const FinishLds &F,
+                        uint32_t stamp)
 {
-    __shared__ int s_nf;
-    __shared__ int s_pred;
-    constexpr int NW = T / kWave;
+    constexpr int T = Team::kSize;
+    constexpr int NW = Team::kWaves;
     LX_GLOBAL const uint64_t *bits = as_global(g.bits);
     LX_GLOBAL const int32_t *rp = as_global(g.rp);
     LX_GLOBAL const int32_t *ci = as_global(g.ci);
     LX_GLOBAL int32_t *level = as_global(g.level);
     LX_GLOBAL int32_t *q = as_global(g.q0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t *amask = F.amask, *vis = F.vis, *nxt = F.nxt;
+    int32_t *s_nf = F.sc, *s_pred = F.sc + 1;
+    const int tid = tm.tid, lane = tid & 63, wave = tid >> 6;
     const int wn = g.wn;
     const uint64_t tail = (g.n & 63) ? ((1ull << (g.n & 63)) - 1ull) : ~0ull;
     LX_GLOBAL const uint64_t *rowc = bits + (int64_t)c * g.W;
@@ -195,23 +193,23 @@ __device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path, 
         nxt[w] = vis[w];
     }
     if (tid == 0) level[src] = (int32_t)(stamp << 16);
-    __syncthreads();
+    tm.sync();
     int d = 0;
     for (;;) {
         // The frontier (nxt) as a list of ids in q.
-        if (tid == 0) s_nf = 0;
-        __syncthreads();
+        if (tid == 0) *s_nf = 0;
+        tm.sync();
         for (int w = tid; w < wn; w += T) {
             uint64_t f = nxt[w];
             if (!f) continue;
-            int p = atomicAdd(&s_nf, __popcll(f));
+            int p = atomicAdd(s_nf, __popcll(f));
             for (; f; f &= f - 1) q[p++] = (w << 6) + ctz64(f);
         }
-        block_sync_agent();
-        const int nf = s_nf;
+        tm.sync_agent();
+        const int nf = *s_nf;
         if (nf == 0) return 0;  // dst unreachable
         for (int w = tid; w < wn; w += T) nxt[w] = 0ull;
-        __syncthreads();
+        tm.sync();
         // Next layer: OR of the frontier's rows, masked.
         for (int f0 = wave; f0 < nf; f0 += 4 * NW) {
             const int u0 = q[f0];
@@ -227,9 +225,9 @@ __device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path, 
                 if (acc) atomicOr((unsigned long long *)&nxt[w], acc);
             }
         }
-        __syncthreads();
+        tm.sync();
         ++d;
-        int found = 0;
+        bool found = false;
         for (int w = tid; w < wn; w += T) {
             const uint64_t nw = nxt[w];
             if (!nw) continue;
@@ -240,52 +238,59 @@ __device__ int bfs_path(const GDesc &g, int c, int src, int dst, int32_t *path, 
                 found |= u == dst;
             }
         }
-        if (__syncthreads_or(found)) break;
+        if (tm.any_all(found)) break;
     }
-    block_sync_agent();  // levels visible to every lane
+    tm.sync_agent();  // levels visible to every lane
     if (tid == 0) path[d] = dst;
     int y = dst;
     for (int l = d; l >= 1; --l) {
-        if (tid == 0) s_pred = INT_MAX;
-        __syncthreads();
+        if (tid == 0) *s_pred = INT_MAX;
+        tm.sync();
         const int32_t want = (int32_t)((stamp << 16) | (uint32_t)(l - 1));
         const int e = rp[y + 1];
         for (int j = rp[y] + tid; j < e; j += T) {  // rows ascend: first hit per lane is its minimum
             const int u = ci[j];
             if ((unsigned)u < (unsigned)g.n && level[u] == want) {
-                atomicMin(&s_pred, u);
+                atomicMin(s_pred, u);
                 break;
             }
         }
-        __syncthreads();
-        y = s_pred;
-        __syncthreads();
+        tm.sync();
+        y = *s_pred;
+        tm.sync();
         if (y == INT_MAX) return 0;  // only with a non-symmetric CSR
         if (tid == 0) path[l - 1] = y;
     }
     return d + 1;
 }
 
-// Witness and certificate for one graph; all threads of the block call it.
-template <int T>
-__device__ void finish_graph(const GDesc &g, uint32_t flags, uint64_t *lds)
+__device__ __forceinline__ void write_result(lexbfs_result_t *out, int chordal, int v, int p, int z, int len, int fb)
 {
-    uint64_t *amask = lds, *vis = lds + g.wn, *nxt = lds + 2 * g.wn;
+    lexbfs_result_t r;
+    r.chordal = chordal;
+    r.witness_v = v;
+    r.witness_p = p;
+    r.witness_z = z;
+    r.cycle_len = len;
+    r.fallback = fb;
+    r.reserved[0] = r.reserved[1] = 0;
+    *out = r;
+}
+
+// Witness and certificate for one graph; every lane of the team calls it
+// after the failing rank (failkey), order, rank and parent are visible.
+template <class Team>
+__device__ void finish_graph(const Team &tm, const GDesc &g, uint32_t flags, const FinishLds &F)
+{
+    constexpr int T = Team::kSize;
+    constexpr int NW = Team::kWaves;
+    uint32_t *s_red = (uint32_t *)(F.sc + 2);
+    int32_t *s_wcnt = F.sc + 2 + NW;
     uint32_t stamp = 0;
-    __shared__ uint32_t s_red[T / kWave];
-    __shared__ uint32_t s_wcnt[T / kWave];
-    const int tid = threadIdx.x;
+    const int tid = tm.tid;
     const uint32_t fk = g.n > 0 ? g_load(g.failkey) : kNoFail;
     if (fk == kNoFail) {
-        if (tid == 0) {
-            lexbfs_result_t r;
-            r.chordal = 1;
-            r.witness_v = r.witness_p = r.witness_z = -1;
-            r.cycle_len = 0;
-            r.fallback = 0;
-            r.reserved[0] = r.reserved[1] = 0;
-            *g.res = r;
-        }
+        if (tid == 0) write_result(g.res, 1, -1, -1, -1, 0, 0);
         return;
     }
     const int v = g.order[fk];
@@ -302,30 +307,20 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags, uint64_t *lds)
             if ((int)rz < rx) best = min(best, rz);
         }
     }
-    best = block_min_u32<T>(best, s_red);
+    best = tm.min_all(best, s_red);
     if (best >= (uint32_t)g.n) {
         // Only reachable when the input breaks its contract (e.g. an
         // asymmetric bitset): report the failure without a certificate.
-        if (tid == 0) {
-            lexbfs_result_t r;
-            r.chordal = 0;
-            r.witness_v = v;
-            r.witness_p = x;
-            r.witness_z = -1;
-            r.cycle_len = 0;
-            r.fallback = 0;
-            r.reserved[0] = r.reserved[1] = 0;
-            *g.res = r;
-        }
+        if (tid == 0) write_result(g.res, 0, v, x, -1, 0, 0);
         return;
     }
     const int z = g.order[best];
 
     for (int u = tid; u < g.n; u += T) g.level[u] = 0;  // stamp 0: never matches a search
-    block_sync_agent();
+    tm.sync_agent();
     int len = 0, fb = 0;
     if (!(flags & LEXBFS_FLAG_FORCE_FALLBACK)) {
-        len = bfs_path<T>(g, v, x, z, g.cycle + 1, amask, vis, nxt, ++stamp);
+        len = bfs_path(tm, g, v, x, z, g.cycle + 1, F, ++stamp);
         if (len > 0) {
             if (tid == 0) g.cycle[0] = v;
             len += 1;
@@ -344,18 +339,18 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags, uint64_t *lds)
                 const int r = base + tid;
                 const bool in = r < rv && test_bit(row2, g.order[r]);
                 const uint64_t bal = __ballot(in);
-                if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(bal);
-                __syncthreads();
+                if (lane == 0) s_wcnt[wave] = __popcll(bal);
+                tm.sync();
                 int off = k, total = 0;
-                for (int w = 0; w < T / kWave; ++w) {
-                    if (w < wave) off += (int)s_wcnt[w];
-                    total += (int)s_wcnt[w];
+                for (int w = 0; w < NW; ++w) {
+                    if (w < wave) off += s_wcnt[w];
+                    total += s_wcnt[w];
                 }
                 if (in) g_store_i(&g.lnbuf[off + __popcll(bal & lanemask_lt(lane))], g.order[r]);
                 k += total;
-                __syncthreads();
+                tm.sync();
             }
-            block_sync_agent();
+            tm.sync_agent();
             for (int ia = 0; ia < k && len == 0; ++ia) {
                 const int a = g_load_i(&g.lnbuf[ia]);
                 const uint64_t *rowa = g.bits + (int64_t)a * g.W;
@@ -364,10 +359,10 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags, uint64_t *lds)
                     if (test_bit(rowa, b)) continue;
                     if (stamp == 0xFFFFu) {  // stamps exhausted: clear the levels, start over
                         for (int u = tid; u < g.n; u += T) g.level[u] = 0;
-                        block_sync_agent();
+                        tm.sync_agent();
                         stamp = 0;
                     }
-                    len = bfs_path<T>(g, v2, b, a, g.cycle + 1, amask, vis, nxt, ++stamp);
+                    len = bfs_path(tm, g, v2, b, a, g.cycle + 1, F, ++stamp);
                     if (len > 0) {
                         if (tid == 0) g.cycle[0] = v2;
                         len += 1;
@@ -376,17 +371,7 @@ __device__ void finish_graph(const GDesc &g, uint32_t flags, uint64_t *lds)
             }
         }
     }
-    if (tid == 0) {
-        lexbfs_result_t r;
-        r.chordal = 0;
-        r.witness_v = v;
-        r.witness_p = x;
-        r.witness_z = z;
-        r.cycle_len = len;
-        r.fallback = fb;
-        r.reserved[0] = r.reserved[1] = 0;
-        *g.res = r;
-    }
+    if (tid == 0) write_result(g.res, 0, v, x, z, len, fb);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,14 +411,144 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep_single(GDesc g, int row
 __global__ __launch_bounds__(kFinishThreads) void k_finish_single(GDesc g, uint32_t flags)
 {
     extern __shared__ uint64_t lds[];
-    finish_graph<kFinishThreads>(g, flags, lds);
+    BlockTeam<kFinishThreads, false> tm{(int)threadIdx.x};
+    finish_graph(tm, g, flags, carve_finish(lds, g.wn, kFinishThreads / kWave));
+}
+
+// ---------------------------------------------------------------------------
+// LexBFS with one round of launches per step (the host loop of Section 6.1:
+// a fixed sequence of kernels per step, one thread per vertex, every table
+// in global memory). Kept as the comparison form for the persistent kernel.
+// Same class naming as the persistent kernel: a class is the position range
+// [c, clast[c]] named by its start; the pivot's neighbours in c move to the
+// top cnt[c] positions (Observation 6.2), so the top class is the largest
+// class id and the pivot is the unnumbered vertex of largest
+// (class, -id) key, kept as (class << 32 | 0xFFFFFFFF - id) in a 64-bit max.
+//   count:  number the pivot, shrink its class, count neighbours per class
+//   assign: neighbours take their class's new upper part
+//   close:  the first-counted neighbour of each class shrinks the old class;
+//           every unnumbered vertex offers its key for the next pivot
+// ---------------------------------------------------------------------------
+struct StepTabs {
+    uint32_t *cls;            // class of each vertex
+    uint32_t *clast;          // last position of each live class
+    uint32_t *cnt;            // neighbours of the pivot per class
+    int32_t *lead;            // class counted first by this vertex, or -1
+    unsigned long long *key;  // [2]: pivot key of this step and the next
+};
+
+constexpr int kStepThreads = 256;
+
+__device__ __forceinline__ int step_pivot(const StepTabs &st, int i)
+{
+    return (int)(0xFFFFFFFFu - (uint32_t)st.key[i & 1]);  // written by the previous launch
+}
+
+__device__ __forceinline__ bool adjacent_bit(const GDesc &g, int x, int v)
+{
+    return (g.bits[(size_t)x * (size_t)g.W + (size_t)(v >> 6)] >> (v & 63)) & 1ull;
+}
+
+__global__ __launch_bounds__(kStepThreads) void k_step_init(GDesc g, StepTabs st)
+{
+    const int v = blockIdx.x * kStepThreads + threadIdx.x;
+    if (v < g.n) {
+        st.cls[v] = 0;
+        st.cnt[v] = 0;
+        st.lead[v] = -1;
+        g.rank[v] = -1;
+        g.parent[v] = -1;
+    }
+    if (v == 0) {
+        st.clast[0] = (uint32_t)(g.n - 1);
+        st.key[0] = 0xFFFFFFFFull;  // class 0, vertex 0
+        st.key[1] = 0;
+        if (g.failkey) *g.failkey = kNoFail;
+    }
+}
+
+__global__ __launch_bounds__(kStepThreads) void k_step_count(GDesc g, StepTabs st, int i)
+{
+    const int x = step_pivot(st, i);
+    const int v = blockIdx.x * kStepThreads + threadIdx.x;
+    if (v == 0) {
+        g.order[i] = x;
+        g.rank[x] = i;
+        st.key[(i + 1) & 1] = 0;
+        const uint32_t top = (uint32_t)(g.n - 1 - i);  // the pivot's class ends here
+        const uint32_t c = st.cls[x];
+        if (c < top) st.clast[c] = top - 1;
+    }
+    if (v >= g.n || v == x || g.rank[v] >= 0 || !adjacent_bit(g, x, v)) return;
+    const uint32_t c = st.cls[v];
+    const uint32_t before = atomicAdd(&st.cnt[c], 1u);
+    st.lead[v] = before == 0 ? (int32_t)c : -1;
+    g.parent[v] = x;
+}
+
+__global__ __launch_bounds__(kStepThreads) void k_step_assign(GDesc g, StepTabs st, int i)
+{
+    const int x = step_pivot(st, i);
+    const int v = blockIdx.x * kStepThreads + threadIdx.x;
+    if (v >= g.n || v == x || g.rank[v] >= 0 || !adjacent_bit(g, x, v)) return;
+    const uint32_t c = st.cls[v];
+    const uint32_t last = st.clast[c];
+    const uint32_t nw = last + 1 - st.cnt[c];
+    if (nw != c) {
+        st.cls[v] = nw;
+        // Positions above c inside its range are no live class's start, so
+        // no thread of this launch reads clast[nw].
+        if (st.lead[v] >= 0) st.clast[nw] = last;
+    }
+}
+
+__global__ __launch_bounds__(kStepThreads) void k_step_close(GDesc g, StepTabs st, int i)
+{
+    __shared__ unsigned long long red[kStepThreads / kWave];
+    const int v = blockIdx.x * kStepThreads + threadIdx.x;
+    unsigned long long k = 0;
+    if (v < g.n) {
+        const int32_t c = st.lead[v];
+        if (c >= 0) {
+            st.lead[v] = -1;
+            const uint32_t nw = st.cls[v];
+            if (nw != (uint32_t)c) st.clast[c] = nw - 1;
+            st.cnt[c] = 0;
+        }
+        if (g.rank[v] < 0) k = ((unsigned long long)st.cls[v] << 32) | (0xFFFFFFFFu - (uint32_t)v);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(k, o, kWave);
+        k = y > k ? y : k;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kStepThreads / kWave; ++w) k = red[w] > k ? red[w] : k;
+        if (k) atomicMax(&st.key[(i + 1) & 1], k);
+    }
+}
+
+// One graph of a batch on one team, start to finish: LexBFS with the fused
+// elimination test, then (for a failing graph) the witness and certificate,
+// reusing the team's LDS region.
+template <class Team>
+__device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32_t flags)
+{
+    BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
+    lexbfs_team<Team, LdsTables<true>, true>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, B.L.starts,
+                                              B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
+    tm.sync_agent();  // order, rank, parent and the failing rank visible to the team
+    finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
+    tm.sync();        // the region is reused by the team's next graph
 }
 
 // Batch: every block first takes large graphs (whole block per graph) from a
 // longest-first queue; once those run out every wave takes small graphs.
 template <int BT>
-__global__ __launch_bounds__(BT) void k_lexbfs_batch(const GDesc *__restrict__ gds, const int32_t *__restrict__ sorted,
-                                                     int nbig, int count, uint32_t *qctr, int wave_region_bytes)
+__global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, const int32_t *__restrict__ sorted,
+                                              int nbig, int count, uint32_t *qctr, int wave_region_bytes,
+                                              uint32_t flags)
 {
     extern __shared__ uint64_t lds[];
     __shared__ int s_idx;
@@ -443,11 +558,8 @@ __global__ __launch_bounds__(BT) void k_lexbfs_batch(const GDesc *__restrict__ g
         const int k = s_idx;
         __syncthreads();
         if (k >= nbig) break;
-        const GDesc g = gds[sorted[k]];
-        LdsLayout<true> L = carve_lds<true>(lds, g.n, BT);
         BlockTeam<BT, false> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
-        __syncthreads();
+        batch_graph(tm, gds[sorted[k]], lds, flags);
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     void *region = (char *)lds + (size_t)wave * wave_region_bytes;
@@ -457,11 +569,8 @@ __global__ __launch_bounds__(BT) void k_lexbfs_batch(const GDesc *__restrict__ g
         if (lane == 0) k = (int)atomicAdd(&qctr[1], 1u);
         k = __shfl(k, 0, kWave);
         if (k >= nsmall) break;
-        const GDesc g = gds[sorted[nbig + k]];
-        LdsLayout<true> L = carve_lds<true>(region, g.n, kWave);
         WaveTeam tm{lane};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
-        tm.sync();
+        batch_graph(tm, gds[sorted[nbig + k]], region, flags);
     }
 }
 
@@ -473,26 +582,6 @@ __global__ void k_batch_init(const GDesc *__restrict__ gds, int count, uint32_t 
         qctr[0] = 0;
         qctr[1] = 0;
     }
-}
-
-__global__ __launch_bounds__(kSweepThreads) void k_sweep_batch(const GDesc *__restrict__ gds,
-                                                               const SweepItem *__restrict__ items)
-{
-    const SweepItem it = items[blockIdx.x];
-    const GDesc &g = gds[it.g];
-    int G = 1, lg = 0;
-    while (G < g.wn && G < kWave) {
-        G <<= 1;
-        ++lg;
-    }
-    sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, it.r0, it.r1, G, lg, g.failkey);
-}
-
-__global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const GDesc *__restrict__ gds, uint32_t flags)
-{
-    extern __shared__ uint64_t lds[];
-    const GDesc g = gds[blockIdx.x];
-    finish_graph<kFinishThreads>(g, flags, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,6 +725,31 @@ int launch_lexbfs_single(const GDesc &d, hipStream_t s)
     }
 }
 
+// The per-step form: three launches per step over ceil(n / 256) blocks.
+// Its tables live in the certificate's scratch arrays (not yet in use) and
+// the global class-table area of the workspace.
+int launch_lexbfs_per_step(const GDesc &d, hipStream_t s)
+{
+    StepTabs st;
+    st.cls = (uint32_t *)d.q0;
+    st.lead = d.q1;
+    st.clast = d.gtab;
+    st.cnt = d.gtab + d.n;
+    st.key = (unsigned long long *)d.lnbuf;  // 2 x 8 bytes of a >= 256-byte array
+    const dim3 grid((d.n + kStepThreads - 1) / kStepThreads), block(kStepThreads);
+    ProfScope ps(0, s);
+    hipLaunchKernelGGL(k_step_init, grid, block, 0, s, d, st);
+    LX_CHECK_LAUNCH("per-step LexBFS init launch");
+    for (int i = 0; i < d.n; ++i) {
+        hipLaunchKernelGGL(k_step_count, grid, block, 0, s, d, st, i);
+        if (i + 1 == d.n) break;  // nothing left to split or choose
+        hipLaunchKernelGGL(k_step_assign, grid, block, 0, s, d, st, i);
+        hipLaunchKernelGGL(k_step_close, grid, block, 0, s, d, st, i);
+    }
+    LX_CHECK_LAUNCH("per-step LexBFS launches");
+    return LEXBFS_OK;
+}
+
 void sweep_shape(int wn, int &G, int &lg)
 {
     G = 1;
@@ -650,7 +764,13 @@ void sweep_shape(int wn, int &G, int &lg)
 int sweep_rows_per_block(int G) { return (kSweepThreads / kWave) * (kWave / G) * 4; }
 
 // Dynamic LDS of the certificate kernel: three bitsets of wn words.
-size_t finish_lds(int wn) { return 3 * 8 * (size_t)(wn > 0 ? wn : 1); }
+size_t finish_lds(int wn) { return finish_lds_bytes(wn, kFinishThreads / kWave); }
+
+// LDS of one batch team: its LexBFS state, later reused by the certificate.
+size_t batch_region_bytes(int n, int team)
+{
+    return align_up(std::max(lds_bytes_batch(n, team), finish_lds_bytes((n + 63) / 64, team / kWave)), 16);
+}
 
 GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *order, int32_t *rank,
                 int32_t *parent, int32_t *cycle, lexbfs_result_t *res)
@@ -678,34 +798,21 @@ GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *o
 
 // Batch plan kept in the workspace.
 struct BatchWs {
-    size_t qctr, gds, sorted, items, failkeys, arrays, total;
-    int nitems;
+    size_t qctr, gds, sorted, failkeys, arrays, total;
 };
-
-int batch_items_for(int n, int wn)
-{
-    int G, lg;
-    sweep_shape(wn, G, lg);
-    const int rpb = sweep_rows_per_block(G);
-    return (n + rpb - 1) / rpb;
-}
 
 BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
 {
     BatchWs L;
     size_t off = 0;
-    int nitems = 0;
     size_t arrays = 0;
     for (int i = 0; i < count; ++i) {
         const int n = gs[i].n;
-        nitems += n > 0 ? batch_items_for(n, (n + 63) / 64) : 0;
         arrays += 8 * al((size_t)(n > 0 ? n : 1) * 4);
     }
-    L.nitems = nitems;
     L.qctr = off; off += kAlign;
     L.gds = off; off += al(sizeof(GDesc) * (size_t)count);
     L.sorted = off; off += al(4 * (size_t)count);
-    L.items = off; off += al(sizeof(SweepItem) * (size_t)(nitems > 0 ? nitems : 1));
     L.failkeys = off; off += al(4 * (size_t)count);
     L.arrays = off; off += arrays;
     L.total = off;
@@ -723,11 +830,9 @@ struct lexbfs_batch_plan {
     BatchWs L{};
     std::vector<char> table;
     int nbig = 0;
-    int nitems = 0;
     size_t lds = 0;
     int region = 0;
     int blocks = 1;
-    size_t finish_lds = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -816,7 +921,7 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
     const GDesc d = make_desc(g, (char *)ws, L, out ? out->order : nullptr, out ? out->rank : nullptr,
                               out ? out->parent : nullptr, out ? out->cycle : nullptr, res);
     if (g->n > 0) {
-        rc = launch_lexbfs_single(d, s);
+        rc = (flags & LEXBFS_FLAG_PER_STEP) ? launch_lexbfs_per_step(d, s) : launch_lexbfs_single(d, s);
         if (rc) return rc;
         int G, lg;
         sweep_shape(d.wn, G, lg);
@@ -853,13 +958,14 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
     if (tuning) {
         if (tuning->block_threads != 0 && tuning->block_threads != BT) return LEXBFS_EINVAL;
         if (tuning->wave_max_n > 0) wave_max_n = tuning->wave_max_n;
+        if (tuning->wave_max_n < 0) wave_max_n = 0;  // every graph on a workgroup
     }
     wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
     {
         // Every wave of a workgroup needs its own region: keep the wave
         // threshold where four regions fit the LDS of one workgroup.
-        const size_t lim = dynamic_lds_limit(k_lexbfs_batch<BT>);
-        while (wave_max_n > 64 && (size_t)(BT / kWave) * lds_bytes_lds_tables(wave_max_n, kWave, true) > lim)
+        const size_t lim = dynamic_lds_limit(k_batch<BT>);
+        while (wave_max_n > 64 && (size_t)(BT / kWave) * batch_region_bytes(wave_max_n, kWave) > lim)
             wave_max_n -= 64;
     }
     int maxn_block = 0, maxn_wave = 0;
@@ -882,13 +988,13 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
         *plan_out = P;
         return LEXBFS_OK;
     }
-    const size_t maxl = dynamic_lds_limit(k_lexbfs_batch<BT>);
+    const size_t maxl = dynamic_lds_limit(k_batch<BT>);
     if (!maxl) {
         delete P;
         return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
     }
-    const size_t region = maxn_wave > 0 ? lds_bytes_lds_tables(maxn_wave, kWave, true) : 0;
-    size_t lds = std::max(lds_bytes_lds_tables(std::max(maxn_block, 1), BT, true), region * (BT / kWave));
+    const size_t region = maxn_wave > 0 ? batch_region_bytes(maxn_wave, kWave) : 0;
+    size_t lds = std::max(batch_region_bytes(std::max(maxn_block, 1), BT), region * (BT / kWave));
     if (tuning && tuning->lds_bytes > 0) lds = std::max(lds, (size_t)tuning->lds_bytes);
     if (lds > maxl) {
         delete P;
@@ -896,11 +1002,10 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
     }
     char *w = (char *)ws;
 
-    // Host plan: descriptors, longest-first order, sweep items.
+    // Host plan: descriptors and the longest-first order.
     P->table.resize(L.failkeys - L.gds);
     GDesc *hd = (GDesc *)P->table.data();
     int32_t *hsorted = (int32_t *)(P->table.data() + (L.sorted - L.gds));
-    SweepItem *hitems = (SweepItem *)(P->table.data() + (L.items - L.gds));
     size_t aoff = L.arrays;
     for (int i = 0; i < count; ++i) {
         const lexbfs_graph_t &g = gs[i];
@@ -937,29 +1042,15 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
     std::stable_sort(hsorted, hsorted + count, [&](int a, int b) { return gs[a].n > gs[b].n; });
     int nbig = 0;
     while (nbig < count && gs[hsorted[nbig]].n > wave_max_n) ++nbig;
-    int it = 0;
-    for (int k = 0; k < count; ++k) {  // sweep items, largest graphs first
-        const int i = hsorted[k];
-        const int n = gs[i].n;
-        if (n <= 0) continue;
-        int G, lg;
-        sweep_shape((n + 63) / 64, G, lg);
-        const int rpb = sweep_rows_per_block(G);
-        for (int r0 = 0; r0 < n; r0 += rpb) hitems[it++] = SweepItem{i, r0, std::min(n, r0 + rpb), 0};
-    }
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
     P->nbig = nbig;
-    P->nitems = it;
     P->lds = lds;
     P->region = (int)region;
     P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
-    int maxwn = 1;
-    for (int i = 0; i < count; ++i) maxwn = std::max(maxwn, (gs[i].n + 63) / 64);
-    P->finish_lds = finish_lds(maxwn);
     const hipError_t e =
         hipMemcpyAsync(w + L.gds, P->table.data(), P->table.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e != hipSuccess) {
@@ -986,27 +1077,28 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
     LX_CHECK_LAUNCH("batch init launch");
     {
         ProfScope ps(0, s);
-        hipLaunchKernelGGL((k_lexbfs_batch<BT>), dim3(P->blocks), dim3(BT), P->lds, s, dg,
-                           (const int32_t *)(w + P->L.sorted), P->nbig, P->count, qctr, P->region);
+        hipLaunchKernelGGL((k_batch<BT>), dim3(P->blocks), dim3(BT), P->lds, s, dg,
+                           (const int32_t *)(w + P->L.sorted), P->nbig, P->count, qctr, P->region, P->flags);
     }
-    LX_CHECK_LAUNCH("batch LexBFS launch");
-    if (P->nitems > 0) {
-        {
-            ProfScope ps(1, s);
-            hipLaunchKernelGGL(k_sweep_batch, dim3(P->nitems), dim3(kSweepThreads), 0, s, dg,
-                               (const SweepItem *)(w + P->L.items));
-        }
-        LX_CHECK_LAUNCH("batch sweep launch");
-    }
-    {
-        ProfScope ps(2, s);
-        hipLaunchKernelGGL(k_finish_batch, dim3(P->count), dim3(kFinishThreads), P->finish_lds, s, dg, P->flags);
-    }
-    LX_CHECK_LAUNCH("batch certificate launch");
+    LX_CHECK_LAUNCH("batch launch");
     return LEXBFS_OK;
 }
 
 void lexbfs_batch_plan_destroy(lexbfs_batch_plan_t *plan) { delete plan; }
+
+int32_t lexbfs_batch_max_n(void)
+{
+    constexpr int BT = kBatchThreads;
+    const size_t lim = dynamic_lds_limit(k_batch<BT>);
+    if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
+    int lo = 0, hi = 64 * BT;  // largest n in [lo, hi] whose team state fits
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (batch_region_bytes(mid, BT) <= lim) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
                        lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,

@@ -172,6 +172,24 @@ __device__ __forceinline__ uint32_t dpp_max32_step(uint32_t v)
     return o > v ? o : v;
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_add32_step(uint32_t v)
+{
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+
+// Sum over the 64 lanes with DPP (all lanes active); the result is uniform.
+__device__ __forceinline__ uint32_t wave_sum_dpp(uint32_t v)
+{
+    v = dpp_add32_step<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_add32_step<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_add32_step<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_add32_step<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_add32_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add32_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ uint32_t wave_max_dpp(uint32_t v)
 {
     v = dpp_max32_step<0x111, 0xF>(v);  // row_shr:1
@@ -201,6 +219,29 @@ struct WaveTeam {
         sync();
         return v;
     }
+    // Max of v and sum of s over the team at once; the sum is returned in s.
+    __device__ __forceinline__ uint32_t max_sum_all(uint32_t v, uint32_t &s, uint32_t *) const
+    {
+        v = wave_max_dpp(v);
+        s = wave_sum_dpp(s);
+        sync();
+        return v;
+    }
+    // Barrier that also makes global stores of every lane visible to every
+    // lane (agent-scope release and acquire around it).
+    __device__ __forceinline__ void sync_agent() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __device__ __forceinline__ uint32_t min_all(uint32_t v, uint32_t *) const
+    {
+        v = wave_min_u32(v);
+        sync();
+        return v;
+    }
+    __device__ __forceinline__ bool any_all(bool p) const { return __ballot(p) != 0ull; }
 };
 
 // On gfx950 a workgroup barrier waits for LDS traffic only; global loads in
@@ -230,6 +271,44 @@ struct BlockTeam {
         for (int k = 1; k < kWaves; ++k) r = max(r, red[k]);
         return r;
     }
+    // Max of v and sum of s (returned in s); red: 2 * T/64 LDS words.
+    __device__ __forceinline__ uint32_t max_sum_all(uint32_t v, uint32_t &s, uint32_t *red) const
+    {
+        v = wave_max_dpp(v);
+        s = wave_sum_dpp(s);
+        if ((tid & 63) == 0) {
+            red[tid >> 6] = v;
+            red[kWaves + (tid >> 6)] = s;
+        }
+        sync();
+        uint32_t r = red[0], q = red[kWaves];
+#pragma unroll
+        for (int k = 1; k < kWaves; ++k) {
+            r = max(r, red[k]);
+            q += red[kWaves + k];
+        }
+        s = q;
+        return r;
+    }
+    __device__ __forceinline__ void sync_agent() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    // Min over the team; red: T/64 LDS words, free again after return.
+    __device__ __forceinline__ uint32_t min_all(uint32_t v, uint32_t *red) const
+    {
+        v = wave_min_u32(v);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        uint32_t r = red[0];
+#pragma unroll
+        for (int k = 1; k < kWaves; ++k) r = min(r, red[k]);
+        __syncthreads();
+        return r;
+    }
+    __device__ __forceinline__ bool any_all(bool p) const { return __syncthreads_or(p) != 0; }
 };
 
 // ---------------------------------------------------------------------------
@@ -247,6 +326,7 @@ struct LdsTables {
     uint16_t *clast;
     uint32_t *cnt;
     static constexpr bool kRem = kWithRem;
+    static constexpr bool kInLds = true;
     __device__ __forceinline__ uint32_t last(uint32_t c) const { return clast[c]; }
     __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { clast[c] = (uint16_t)v; }
     __device__ __forceinline__ uint32_t word(uint32_t c) const { return cnt[c]; }
@@ -260,6 +340,7 @@ struct GlobalTables {
     uint32_t *clast;
     uint32_t *cnt;
     static constexpr bool kRem = false;
+    static constexpr bool kInLds = false;
     __device__ __forceinline__ uint32_t last(uint32_t c) const { return g_load(&clast[c]); }
     __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { g_store(&clast[c], v); }
     __device__ __forceinline__ uint32_t word(uint32_t c) const { return g_load(&cnt[c]); }
@@ -274,6 +355,16 @@ struct GlobalTables {
     }
 };
 
+// Optional parts of the LexBFS state for the fused elimination test: the
+// parent of every vertex in LDS (16 bits, kNoParent = none) and one word
+// for the smallest failing rank.
+struct FusedPeo {
+    uint16_t *par;     // [n] in LDS
+    uint32_t *fk;      // one LDS word
+    uint32_t *failkey; // global result word of the graph
+};
+constexpr uint16_t kNoParent = 0xFFFFu;
+
 __host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // LDS of one graph's state. Tables in LDS:
@@ -286,14 +377,14 @@ __host__ __device__ inline size_t lds_bytes_lds_tables(int n, int team, bool wit
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
     const size_t a = align_up(2 * (size_t)n, 16);
-    return align_up(8 * wn, 16) + align_up(8 * nred, 16) + 2 * a + align_up(4 * (size_t)n, 16) + (with_rem ? a : 0);
+    return align_up(8 * wn, 16) + align_up(16 * nred, 16) + 2 * a + align_up(4 * (size_t)n, 16) + (with_rem ? a : 0);
 }
 
 __host__ __device__ inline size_t lds_bytes_global_tables(int n, int team)
 {
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
-    return align_up(8 * wn, 16) + align_up(8 * nred, 16) + align_up(2 * (size_t)n, 16);
+    return align_up(8 * wn, 16) + align_up(16 * nred, 16) + align_up(2 * (size_t)n, 16);
 }
 
 template <bool kWithRem>
@@ -316,12 +407,35 @@ __device__ __forceinline__ LdsLayout<kWithRem> carve_lds(void *base, int n, int 
     L.starts = (uint64_t *)p;
     p += align_up(8 * wn, 16);
     L.red = (uint32_t *)p;
-    p += align_up(8 * nred, 16);
+    p += align_up(16 * nred, 16);
     L.cls = (uint16_t *)p;
     L.tab.clast = (uint16_t *)(p + a);
     L.tab.cnt = (uint32_t *)(p + 2 * a);
     L.rem = kWithRem ? (uint16_t *)(p + 2 * a + align_up(4 * (size_t)n, 16)) : nullptr;
     return L;
+}
+
+// Batch graph state: the LDS tables with rem, then the parents and the
+// failing-rank word of the fused elimination test.
+__host__ __device__ inline size_t lds_bytes_batch(int n, int team)
+{
+    return lds_bytes_lds_tables(n, team, true) + align_up(2 * (size_t)n, 16) + 16;
+}
+
+struct BatchLayout {
+    LdsLayout<true> L;
+    FusedPeo fp;
+};
+
+__device__ __forceinline__ BatchLayout carve_batch(void *base, int n, int team, uint32_t *failkey)
+{
+    BatchLayout B;
+    B.L = carve_lds<true>(base, n, team);
+    char *p = (char *)base + lds_bytes_lds_tables(n, team, true);
+    B.fp.par = (uint16_t *)p;
+    B.fp.fk = (uint32_t *)(p + align_up(2 * (size_t)n, 16));
+    B.fp.failkey = failkey;
+    return B;
 }
 
 struct LdsLayoutG {
@@ -339,7 +453,7 @@ __device__ __forceinline__ LdsLayoutG carve_lds_g(void *base, int n, int team)
     L.starts = (uint64_t *)p;
     p += align_up(8 * wn, 16);
     L.red = (uint32_t *)p;
-    p += align_up(8 * nred, 16);
+    p += align_up(16 * nred, 16);
     L.cls = (uint16_t *)p;
     return L;
 }
@@ -381,15 +495,24 @@ __device__ __forceinline__ uint32_t pick_key(uint64_t top, uint64_t nb, uint32_t
     return 0u;
 }
 
+
 // ---------------------------------------------------------------------------
 // LexBFS on one graph by one team.
 //   row_ptr is read once (initial rem = degree) when the tables are in LDS.
 //   red: 2 * waves LDS words (alternating between consecutive reductions).
+//
+// kPeo fuses the perfect-elimination test of Section 5.2 into the steps:
+// when v = x_i is numbered, its earlier neighbours LN_v are exactly its
+// numbered neighbours and its parent p(v) is the last pivot adjacent to it,
+// so v fails iff (row_v & numbered & ~row_p) \ {p} is not empty. The team
+// loads row_p together with row_v (the parent is known, from LDS, as soon as
+// v is chosen) and keeps the smallest failing rank; parents are collected in
+// LDS and written out at the end. Needs n < 65536 (16-bit parents).
 // ---------------------------------------------------------------------------
-template <class Team, class Tabs>
+template <class Team, class Tabs, bool kPeo = false>
 __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
                             int32_t *order_, int32_t *rank_, int32_t *parent_, uint64_t *starts, uint16_t *cls,
-                            uint16_t *rem, const Tabs &tab, uint32_t *red)
+                            uint16_t *rem, const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{})
 {
     LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
     LX_GLOBAL const int32_t *__restrict__ row_ptr = as_global(row_ptr_);
@@ -417,12 +540,16 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         cls[v] = 0;
         tab.clear(v);
         if (kRem) rem[v] = (uint16_t)(row_ptr[v + 1] - row_ptr[v]);
+        if (kPeo) fp.par[v] = kNoParent;
     }
     for (int w = t; w < wn; w += T) starts[w] = w == 0 ? 1ull : 0ull;  // one class, starting at 0
     // parent[v] is later written only by v's owner lane; the same lane clears it.
-    if (owner)
+    if (!kPeo && owner)
         for (int v = vbase; v < min(vbase + K, n); ++v) parent[v] = -1;
-    if (t == 0) tab.set_last(0, (uint32_t)(n - 1));
+    if (t == 0) {
+        tab.set_last(0, (uint32_t)(n - 1));
+        if (kPeo) *fp.fk = kNoFail;
+    }
     tm.sync();
 
     uint64_t um = owner ? cmask : 0ull;  // my unnumbered vertices (word positions)
@@ -430,65 +557,97 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     uint32_t x = 0;                      // first pivot: vertex 0 (smallest id, all labels empty)
     bool xrem = !kRem || rem[0] > 0;     // does the pivot still have unnumbered neighbours?
     uint64_t rw = (owner && xrem) ? rowbase[0] : 0ull;  // my chunk's word of the pivot's row
+    uint32_t xp = kNoParent;  // the pivot's parent (kPeo)
+    uint64_t rp = 0ull;       // my chunk's word of the parent's row (kPeo)
+    uint32_t xcls = 0;        // the pivot's (post-split) class, derived at selection
     int par = 0;
     int U = n;
     for (int i = 0; i < n; ++i) {
         U -= 1;
-        const uint32_t stop = cls[x];  // the pivot's (post-split) class
+        const uint32_t stop = Tabs::kInLds ? xcls : (uint32_t)cls[x];
+        const bool gone = (int)stop == U;  // x was the last member of the top class
         if (owner && (x >> 6) == (uint32_t)wi) {
             um &= ~(1ull << (x & 63));
             top &= ~(1ull << (x & 63));
         }
         uint64_t nb = rw & um;
+        uint64_t bad = 0ull;  // earlier neighbours of x outside N(p), p excluded
+        if (kPeo && xp != kNoParent) {
+            bad = rw & ~um & cmask & ~rp;
+            if ((xp >> 6) == (uint32_t)wi) bad &= ~(1ull << (xp & 63));
+        }
         // Global stores only after the row word is in: on gfx9 the memory
         // counter covers stores too, so a store issued between the row load
         // and its use would hold up the use until the store completes. The
         // empty asm pins the use of the row here, ahead of the stores.
-        __asm__ volatile("" : "+v"(nb)::"memory");
+        __asm__ volatile("" : "+v"(nb), "+v"(bad)::"memory");
+        if (kPeo && bad) atomicMin(fp.fk, (uint32_t)i);
         if (t == 0) {
-            if ((int)stop < U) tab.set_last(stop, (uint32_t)(U - 1));
+            if (!gone) tab.set_last(stop, (uint32_t)(U - 1));
             else atomicAnd((unsigned long long *)&starts[stop >> 6], ~(1ull << (stop & 63)));  // class gone
             order[i] = (int32_t)x;
             rank[x] = i;
         }
 
         // Phase A: count the neighbours of every hit class; record the parent.
+        uint32_t C0 = 0;  // class of my first neighbour, reused in phase B
         for (uint64_t m = nb; m; m &= m - 1) {
             const int y = (int)wbase + ctz64(m);
             const uint32_t C = cls[y];
-            parent[y] = (int32_t)x;
+            if (m == nb) C0 = C;
+            if (kPeo) fp.par[y] = (uint16_t)x;
+            else parent[y] = (int32_t)x;
             if (kRem) rem[y] = (uint16_t)(rem[y] - 1);
             tab.inc(C);
         }
         if (i + 1 == n) break;
 
-        // Next pivot (see the header comment).
-        uint32_t k = tm.max_all(pick_key(top, nb, wbase), red + par * NW);
-        par ^= 1;
-        if ((k >> 16) == 0) {
-            // The top class is exhausted: its successor is the highest live
-            // class start (the pivot's class was cleared above).
-            uint32_t hi = 0;
-            for (int w = t; w < wn; w += T) {
-                const uint64_t sw = starts[w];
-                if (sw) hi = max(hi, (uint32_t)((w << 6) | (63 - __builtin_clzll(sw))) + 1u);
+        // Next pivot (see the header comment). The candidate class is the top
+        // class, or -- when x emptied it -- the class directly below, i.e.
+        // the one holding position U - 1: the highest class start at or
+        // below U - 1, looked up in at most two bitmap words by every lane
+        // alike (almost always enough), else by the whole team.
+        uint32_t cand = stop;
+        if (gone) {
+            const uint32_t pos = (uint32_t)(U - 1);
+            int w = (int)(pos >> 6);
+            uint64_t sw = starts[w] & (~0ull >> (63 - (pos & 63)));
+            if (!sw && w > 0) sw = starts[--w];
+            if (sw) {
+                cand = ((uint32_t)w << 6) | (uint32_t)(63 - __builtin_clzll(sw));
+            } else {
+                uint32_t hi = 0;
+                for (int w2 = t; w2 < w; w2 += T) {
+                    const uint64_t s2 = starts[w2];
+                    if (s2) hi = max(hi, (uint32_t)((w2 << 6) | (63 - __builtin_clzll(s2))) + 1u);
+                }
+                cand = tm.max_all(hi, red + par * 2 * NW) - 1u;
+                par ^= 1;
             }
-            const uint32_t c1 = tm.max_all(hi, red + par * NW) - 1u;
-            par ^= 1;
-            top = chunk_match(cls, um, c1, vbase, sh, K);
-            k = tm.max_all(pick_key(top, nb, wbase), red + par * NW);
-            par ^= 1;
+            top = chunk_match(cls, um, cand, vbase, sh, K);
         }
+        // One reduction: the selection key (max) and the candidate class's
+        // neighbour count (sum).
+        uint32_t c_adj = (uint32_t)__popcll(top & nb);
+        const uint32_t k = tm.max_sum_all(pick_key(top, nb, wbase), c_adj, red + par * 2 * NW);
+        par ^= 1;
         const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
-        if ((k >> 16) == 2) top &= nb;  // narrowed to the pivot's neighbours
+        const bool adj = (k >> 16) == 2;
+        if (adj) top &= nb;  // narrowed to the pivot's neighbours
+        // The candidate class spans [cand, U - 1]; its c_adj members adjacent
+        // to x move to [U - c_adj, U - 1] and hold the next pivot.
+        xcls = adj ? (uint32_t)U - c_adj : cand;
         const bool nrem = !kRem || rem[xn] > 0;
-        const uint64_t rwn = (owner && nrem) ? rowbase[(int64_t)xn * W] : 0ull;
+        const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
+        const bool need = nrem || pn != kNoParent;  // the test reads row_v even when it splits nothing
+        const uint64_t rwn = (owner && need) ? rowbase[(int64_t)xn * W] : 0ull;
+        const uint64_t rpn = (kPeo && owner && pn != kNoParent) ? rowbase[(int64_t)pn * W] : 0ull;
 
         // Phase B: move the neighbours to the upper part of their class; the
         // last neighbour of a class to leave closes it.
         for (uint64_t m = nb; m; m &= m - 1) {
             const int y = (int)wbase + ctz64(m);
-            const uint32_t C = cls[y];
+            const uint32_t C = m == nb ? C0 : (uint32_t)cls[y];
             const uint32_t c = tab.word(C) & 0xFFFFu;  // final neighbour count of C
             const uint32_t last = tab.last(C);
             const bool split = c < last - C + 1;
@@ -508,7 +667,18 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         if (xrem) tm.sync();  // barrier B: nothing to order when the pivot split nothing
         x = xn;
         rw = rwn;
+        rp = rpn;
+        xp = pn;
         xrem = nrem;
+    }
+    if (kPeo) {
+        tm.sync();
+        if (owner)
+            for (int v = vbase; v < min(vbase + K, n); ++v) {
+                const uint32_t p = fp.par[v];
+                parent[v] = p == kNoParent ? -1 : (int32_t)p;
+            }
+        if (t == 0) g_store(fp.failkey, *fp.fk);
     }
 }
 

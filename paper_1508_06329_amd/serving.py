@@ -24,8 +24,20 @@ import time
 from dataclasses import dataclass, field
 from typing import Callable, Deque, Dict, List, Optional, Sequence
 
-# Largest n the batch kernel runs (64 vertices per lane, 256-lane teams).
-BATCH_MAX_N = 64 * 256
+_batch_max_n = None
+
+
+def batch_max_n() -> int:
+    """Largest n the batch kernel takes on this device (its per-graph state
+    must fit one workgroup's LDS); larger graphs run as single calls."""
+    global _batch_max_n
+    if _batch_max_n is None:
+        from . import _lib
+
+        v = int(_lib.load().lexbfs_batch_max_n())
+        _lib.check(min(v, 0), "lexbfs_batch_max_n")
+        _batch_max_n = v
+    return _batch_max_n
 
 
 def footprint_bytes(n: int, nnz: int, W: Optional[int] = None) -> int:
@@ -189,8 +201,9 @@ class GpuExecutor:
         self.next = (self.next + 1) % len(self.streams)
         dgs, up = self._upload([r.graph for r in reqs])
         s.wait_event(up)
-        small = [i for i, g in enumerate(dgs) if g.n <= BATCH_MAX_N]
-        large = [i for i, g in enumerate(dgs) if g.n > BATCH_MAX_N]
+        lim = batch_max_n()
+        small = [i for i, g in enumerate(dgs) if g.n <= lim]
+        large = [i for i, g in enumerate(dgs) if g.n > lim]
         handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "small": small, "large": []}
         with torch.cuda.stream(s):
             if small:

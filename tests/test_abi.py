@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "lexbfs.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char|void)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|int32_t|size_t|char|void)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -126,3 +126,16 @@ def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, 7):
         assert lib.lexbfs_strerror(code)
     assert lib.lexbfs_abi_version() >= 1
+
+
+def test_python_constants_match_header():
+    import re
+
+    hdr = open(os.path.join(ROOT, "include", "lexbfs.h")).read()
+    defs = {m.group(1): m.group(2) for m in re.finditer(r"#define\s+(LEXBFS_\w+)\s+\(?(-?(?:0x)?[0-9a-fA-F]+)u?\)?", hdr)}
+    checked = 0
+    for name, val in defs.items():
+        if hasattr(_lib, name):
+            assert getattr(_lib, name) == int(val, 0), name
+            checked += 1
+    assert checked >= 8 and "LEXBFS_FLAG_PER_STEP" in defs

@@ -211,3 +211,105 @@ def test_compact_mode_sizes(case):
     else:
         g = gg.from_edges(20000, [])
     check_single(g, tag="compact")
+
+
+# ---------------------------------------------------------------------------
+# Batch schedules: autotuner, block-per-graph only, HIP graph replay
+# ---------------------------------------------------------------------------
+
+def test_block_per_graph_schedule():
+    graphs = gg.config_batch(count=48, lo=32, hi=3000, seed=8)
+    graphs.append(gg.from_edges(0, []))
+    check_batch(graphs, tuning={"wave_max_n": -1}, tag="block per graph")
+
+
+def test_autotuner_picks_a_valid_schedule():
+    from paper_1508_06329_amd import autotune
+
+    graphs = gg.config_batch(count=64, lo=32, hi=4096, seed=9)
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    out = autotune.autotune_batch(dgs, candidates=(-1, 256, 1024), reps=2)
+    say(f"[parity] autotune table {out['ms']}")
+    assert set(out["ms"]) == {-1, 256, 1024}
+    best = out["tuning"]["wave_max_n"]
+    assert out["ms"][best] == min(t for t in out["ms"].values() if t is not None)
+    check_batch(graphs, tuning=out["tuning"], tag="autotuned")
+
+
+def test_batch_plan_hip_graph_replay():
+    graphs = gg.config_batch(count=40, lo=32, hi=2500, seed=10)
+    refs = [oracle.chordal_test(g) for g in graphs]
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    plan = lx.BatchPlan(dgs, outputs=True)
+    say("[parity] hip graph capture of a batch plan")
+    graph = plan.capture()
+    for rep in range(3):
+        plan.res.fill_(-7)  # eager work between replays
+        for t in plan.tens:
+            t["order"].fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        rs = plan.results()
+        for g, r, ref in zip(graphs, rs, refs):
+            assert np.array_equal(r.order.cpu().numpy(), ref.order), (rep, g.name)
+            assert r.chordal == ref.chordal and r.witness == ref.witness, (rep, g.name)
+            assert r.cycle_list == ref.cycle.tolist(), (rep, g.name)
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Per-step launch form of LexBFS (comparison path, LEXBFS_FLAG_PER_STEP)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3, 5, 9, 14, 20, 33, 40, 47])
+def test_per_step_structured(idx):
+    cases = structured_cases()
+    g = cases[idx % len(cases)]
+    check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="per-step")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_per_step_random(seed):
+    check_single(gg.gnp(700, 0.01, 70 + seed), flags=lx.LEXBFS_FLAG_PER_STEP, tag="per-step")
+    check_single(gg.plant(gg.subtree(900, 200, 8, seed), 6, seed), flags=lx.LEXBFS_FLAG_PER_STEP, tag="per-step")
+    for g in gg.split_pair(30, 300, 6, 80 + seed):
+        check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="per-step")
+
+
+def test_per_step_workload_small_full():
+    for g in gg.config_single_small():
+        check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="per-step N=1024 workload")
+
+
+def test_per_step_workload_split_65536_full():
+    for g in gg.config_worst_steps():
+        check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="per-step N=65536 split workload")
+
+
+def test_batch_forced_fallback_matches_single():
+    graphs = [gg.gnp(150, 0.04, 90 + s) for s in range(4)] + [gg.plant(gg.subtree(2500, 600, 8, 5), 7, 5)]
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.chordal_test_batch(dgs, outputs=True, flags=lx.LEXBFS_FLAG_FORCE_FALLBACK)
+    for g, dg, r in zip(graphs, dgs, rs):
+        s = lx.chordal_test(dg, flags=lx.LEXBFS_FLAG_FORCE_FALLBACK)
+        assert r.chordal == s.chordal and r.witness == s.witness, g.name
+        assert r.cycle_list == s.cycle_list and r.fallback == s.fallback, g.name
+        if not s.chordal:
+            ref = oracle.chordal_test(g)
+            cyc, fb = oracle.certificate(g, ref.order, ref.rank, ref.witness, force_fallback=True)
+            assert r.cycle_list == cyc.tolist() and fb
+
+
+def test_batch_size_limit():
+    from paper_1508_06329_amd import _lib
+
+    lim = int(_lib.load().lexbfs_batch_max_n())
+    say(f"[parity] batch size limit {lim}")
+    assert 8192 <= lim <= 16384
+    g = gg.plant(gg.subtree(lim - 12, lim // 4, 8, 31), 12, 32)  # exactly the limit
+    assert g.n == lim
+    check_batch([g, gg.gnp(300, 0.02, 33)], tag="at the size limit")
+    big = gg.from_edges(lim + 1, [(i, i + 1) for i in range(lim)])
+    with pytest.raises(lx.LexbfsError):
+        lx.chordal_test_batch([lx.DeviceGraph.from_host(big, DEV)])
