@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--per-graph-sample", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-step", type=int, default=1, help="also time the per-step-launch LexBFS form (single-graph workloads)")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     return ap.parse_args()
 
@@ -290,6 +291,36 @@ def main():
         hipgraph = {"ms_per_step": g_el / args.steps * 1e3, "tests_per_s": len(graphs) * args.steps / g_el}
         log(f"hip graph replay: {hipgraph['tests_per_s']:.1f} tests/s")
 
+    # ---------------- per-step launches (single-graph workloads) ----------------
+    per_step = None
+    if args.workload != "batch" and args.per_step:
+        lib = lx._lib.load()
+        import ctypes
+
+        def step_form():
+            for i, d in enumerate(descs):
+                rc = lib.chordal_test(ctypes.byref(d), res[i].data_ptr(), None, ws[i].data_ptr(), ws[i].numel(),
+                                      lx.LEXBFS_FLAG_PER_STEP, stream.cuda_stream)
+                lx._lib.check(rc, "chordal_test")
+
+        step_form()
+        torch.cuda.synchronize()
+        with lx.KernelTimer() as kt2:
+            t0 = time.perf_counter()
+            step_form()
+            torch.cuda.synchronize()
+            ps_el = time.perf_counter() - t0
+            t2 = kt2.collect()
+        n_steps = sum(g.n for g in graphs)
+        lex_ms = t2["lexbfs"][1]
+        per_step = {"ms_per_step": ps_el * 1e3, "tests_per_s": len(graphs) / ps_el,
+                    "lexbfs_ms_per_graph": lex_ms / len(graphs), "lexbfs_us_per_lexbfs_step": lex_ms * 1e3 / n_steps,
+                    "persistent_lexbfs_ms_per_graph": per_kind["lexbfs"]["avg_ms"],
+                    "persistent_us_per_lexbfs_step": per_kind["lexbfs"]["avg_ms"] * 1e3 * len(graphs) / n_steps}
+        log(f"per-step launches: LexBFS {per_step['lexbfs_ms_per_graph']:.2f} ms/graph "
+            f"({per_step['lexbfs_us_per_lexbfs_step']:.2f} us/step) vs persistent "
+            f"{per_step['persistent_lexbfs_ms_per_graph']:.2f} ms/graph")
+
     # ---------------- per-graph path ----------------
     per_graph = None
     if args.workload == "batch" and args.per_graph_sample > 0:
@@ -364,6 +395,7 @@ def main():
         "roofline": roof,
         "kernels": per_kind,
         "per_graph": per_graph,
+        "per_step_launch": per_step,
         "schedule": tune,
         "hipgraph": hipgraph,
         "cpu_baseline": cpu,
