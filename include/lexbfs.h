@@ -167,10 +167,13 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count);
  * lexbfs_batch_plan_destroy: the per-graph descriptor table is staged into
  * the workspace with a host-to-device copy on `stream`; the calling thread
  * returns once the table has been staged. Every graph needs
- * n <= lexbfs_batch_max_n() (its state must fit one workgroup's LDS).
- * Each graph runs start to finish on one team (a wavefront or a workgroup):
- * LexBFS with the perfect-elimination test of Section 5.2 folded into its
- * steps, then the witness and certificate, so results match chordal_test.
+ * n <= LEXBFS_MAX_N. A graph with n <= lexbfs_batch_max_n() runs start to
+ * finish on one team (a wavefront or a 256-lane workgroup): LexBFS with the
+ * perfect-elimination test of Section 5.2 folded into its steps, then the
+ * witness and certificate. A larger one runs on its own 1024-lane
+ * workgroup: LexBFS, sweep and certificate as in chordal_test (on `stream`,
+ * before the other graphs, in this one-shot call). Results match
+ * chordal_test in every case.
  * Errors: as chordal_test; LEXBFS_ETOOBIG names a graph beyond the limit.
  */
 int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
@@ -179,16 +182,20 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
 
 /*
  * Prepared batches. lexbfs_batch_plan_create validates the graphs, fixes the
- * schedule (longest-first queue, team per graph, sweep work items) and stages
- * the descriptor table into `ws` with a host-to-device copy on `stream`
- * (the call returns once the table has been staged). lexbfs_batch_plan_launch
- * then only launches kernels on `stream`, so it may be called many times
+ * schedule (longest-first queue, team per graph) and stages the descriptor
+ * table into `ws` with a host-to-device copy on `stream` (the call returns
+ * once the table has been staged). lexbfs_batch_plan_launch then only
+ * launches kernels (no copies, no memsets), so it may be called many times
  * (the graphs' contents may change between launches, their sizes and
- * addresses may not) and may be captured into a hipGraph. Results of a
- * launch are valid once the stream reaches it. The plan is host memory owned
- * by the caller until lexbfs_batch_plan_destroy; the workspace must stay
- * allocated while the plan is used and must not be shared by two plans whose
- * launches overlap. Arguments and errors as chordal_test_batch.
+ * addresses may not) and may be captured into a hipGraph. If the batch has
+ * graphs above lexbfs_batch_max_n(), the plan owns a stream and two events
+ * (created here): each launch forks that stream from `stream`, runs those
+ * graphs on it concurrently with the rest, and joins it back into `stream`.
+ * Results of a launch are valid once `stream` reaches it. The plan is host
+ * memory owned by the caller until lexbfs_batch_plan_destroy, which waits for
+ * the plan's own stream; the workspace must stay allocated while the plan is
+ * used and must not be shared by two plans whose launches overlap.
+ * Arguments and errors as chordal_test_batch.
  */
 typedef struct lexbfs_batch_plan lexbfs_batch_plan_t;
 int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
@@ -217,9 +224,10 @@ const char *lexbfs_last_error(void);
 int lexbfs_profile_enable(int on);
 int lexbfs_profile_collect(int32_t *counts, double *ms);
 
-/* Largest n a graph of chordal_test_batch (and of a batch plan) may have on
- * the current device: the team's state must fit one workgroup's LDS
- * (about 12 bytes per vertex). Negative LEXBFS_E* code on a HIP failure. */
+/* Largest n a batch graph may have to run on a wavefront or 256-lane team
+ * on the current device (its state, about 12 bytes per vertex, must fit one
+ * workgroup's LDS); larger graphs, up to LEXBFS_MAX_N, run on 1024-lane
+ * workgroups. Negative LEXBFS_E* code on a HIP failure. */
 int32_t lexbfs_batch_max_n(void);
 
 /* Library ABI version (incremented on incompatible changes). */

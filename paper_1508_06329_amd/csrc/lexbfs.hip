@@ -584,6 +584,40 @@ __global__ void k_batch_init(const GDesc *__restrict__ gds, int count, uint32_t 
     }
 }
 
+// Batch graphs too large for a 256-lane team: one 1024-lane workgroup per
+// graph, with the state of a single-graph call (compact LDS layout when it
+// fits `lds_limit`, else class tables in global memory), then the graph's
+// sweep and certificate on the same workgroup.
+constexpr int kLargeThreads = 1024;
+
+__global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__restrict__ gds,
+                                                               const int32_t *__restrict__ which, uint32_t flags,
+                                                               int lds_limit)
+{
+    extern __shared__ uint64_t lds[];
+    constexpr int T = kLargeThreads;
+    const GDesc g = gds[which[blockIdx.x]];
+    if (lds_bytes_compact(g.n, T) <= (size_t)lds_limit) {
+        BlockTeam<T, false> tm{(int)threadIdx.x};
+        lexbfs_team_compact(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_compact(lds, g.n, T));
+    } else {
+        LdsLayoutG L = carve_lds_g(lds, g.n, T);
+        GlobalTables tab{g.gtab, g.gtab + g.n};
+        BlockTeam<T, true> tm{(int)threadIdx.x};
+        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, nullptr, tab, L.red);
+    }
+    BlockTeam<T, false> tm{(int)threadIdx.x};
+    tm.sync_agent();  // rank and parent of every vertex visible to the sweep
+    int G = 1, lg = 0;
+    while (G < g.wn && G < kWave) {
+        G <<= 1;
+        ++lg;
+    }
+    sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, 0, g.n, G, lg, g.failkey);
+    tm.sync_agent();  // the failing rank visible to the certificate
+    finish_graph(tm, g, flags, carve_finish(lds, g.wn, T / kWave));
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -801,6 +835,23 @@ struct BatchWs {
     size_t qctr, gds, sorted, failkeys, arrays, total;
 };
 
+// Largest n of the 256-lane tier (state in one workgroup's LDS).
+int batch_tier_max_n(size_t lim)
+{
+    int lo = 0, hi = 64 * kBatchThreads;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (batch_region_bytes(mid, kBatchThreads) <= lim) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Per-graph arrays: order, rank, parent, cycle, level, q0, q1, lnbuf, and
+// for graphs too large for any 256-lane team two more for class tables in
+// global memory (used when even the compact LDS layout does not fit).
+int batch_arrays(int n) { return n > 64 * kBatchThreads ? 10 : 8; }
+
 BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
 {
     BatchWs L;
@@ -808,7 +859,7 @@ BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
     size_t arrays = 0;
     for (int i = 0; i < count; ++i) {
         const int n = gs[i].n;
-        arrays += 8 * al((size_t)(n > 0 ? n : 1) * 4);
+        arrays += (size_t)batch_arrays(n) * al((size_t)(n > 0 ? n : 1) * 4);
     }
     L.qctr = off; off += kAlign;
     L.gds = off; off += al(sizeof(GDesc) * (size_t)count);
@@ -829,10 +880,22 @@ struct lexbfs_batch_plan {
     char *ws = nullptr;
     BatchWs L{};
     std::vector<char> table;
-    int nbig = 0;
+    int nbig = 0;    // graphs on 256-lane workgroup teams
+    int nsmall = 0;  // graphs on wavefront teams
+    int nlarge = 0;  // graphs on 1024-lane workgroups (side stream)
     size_t lds = 0;
+    size_t lds_large = 0;
     int region = 0;
     int blocks = 1;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~lexbfs_batch_plan()
+    {
+        if (side) (void)hipStreamSynchronize(side);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -946,9 +1009,10 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
     return batch_layout(gs, count).total;
 }
 
-int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
-                             lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
-                             uint32_t flags, void *stream, lexbfs_batch_plan_t **plan_out)
+namespace {
+int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs, lexbfs_result_t *res,
+                const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes, uint32_t flags, void *stream,
+                bool side_stream, lexbfs_batch_plan_t **plan_out)
 {
     if (!plan_out) return LEXBFS_EINVAL;
     *plan_out = nullptr;
@@ -960,49 +1024,53 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
         if (tuning->wave_max_n > 0) wave_max_n = tuning->wave_max_n;
         if (tuning->wave_max_n < 0) wave_max_n = 0;  // every graph on a workgroup
     }
-    wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
-    {
-        // Every wave of a workgroup needs its own region: keep the wave
-        // threshold where four regions fit the LDS of one workgroup.
-        const size_t lim = dynamic_lds_limit(k_batch<BT>);
-        while (wave_max_n > 64 && (size_t)(BT / kWave) * batch_region_bytes(wave_max_n, kWave) > lim)
-            wave_max_n -= 64;
-    }
-    int maxn_block = 0, maxn_wave = 0;
     for (int i = 0; i < count; ++i) {
         const int rc = validate_graph(&gs[i]);
         if (rc) return rc;
-        if (gs[i].n > wave_max_n) maxn_block = std::max(maxn_block, gs[i].n);
-        else maxn_wave = std::max(maxn_wave, gs[i].n);
     }
-    if (maxn_block > 64 * BT) return fail_code(LEXBFS_ETOOBIG, "a batch graph exceeds 64 vertices per lane");
     const BatchWs L = batch_layout(gs, count);
     if (!ws || ws_bytes < L.total) return LEXBFS_ENOWS;
+    if (count == 0) {
+        lexbfs_batch_plan_t *P = new (std::nothrow) lexbfs_batch_plan_t();
+        if (!P) return fail_code(LEXBFS_EINVAL, "out of host memory for the batch plan");
+        *plan_out = P;
+        return LEXBFS_OK;
+    }
+    const size_t maxl = dynamic_lds_limit(k_batch<BT>);
+    const size_t maxl_large = dynamic_lds_limit(k_batch_large);
+    if (!maxl || !maxl_large) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernels' LDS limits failed");
+    const int tier_max = batch_tier_max_n(maxl);
+    wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
+    // Every wave of a workgroup needs its own region: keep the wave
+    // threshold where four regions fit the LDS of one workgroup.
+    while (wave_max_n > 64 && (size_t)(BT / kWave) * batch_region_bytes(wave_max_n, kWave) > maxl) wave_max_n -= 64;
+    int maxn_block = 0, maxn_wave = 0;
+    for (int i = 0; i < count; ++i) {
+        const int n = gs[i].n;
+        if (n > tier_max) {
+            if (lds_bytes_compact(n, kLargeThreads) > maxl_large && lds_bytes_global_tables(n, kLargeThreads) > maxl_large)
+                return fail_code(LEXBFS_ETOOBIG, "a batch graph's state does not fit the workgroup LDS");
+        } else if (n > wave_max_n) {
+            maxn_block = std::max(maxn_block, n);
+        } else {
+            maxn_wave = std::max(maxn_wave, n);
+        }
+    }
+    const size_t region = maxn_wave > 0 ? batch_region_bytes(maxn_wave, kWave) : 0;
+    size_t lds = std::max(batch_region_bytes(std::max(maxn_block, 1), BT), region * (BT / kWave));
+    if (tuning && tuning->lds_bytes > 0) lds = std::max(lds, (size_t)tuning->lds_bytes);
+    if (lds > maxl) return fail_code(LEXBFS_ETOOBIG, "batch graph state does not fit the workgroup LDS");
     lexbfs_batch_plan_t *P = new (std::nothrow) lexbfs_batch_plan_t();
     if (!P) return fail_code(LEXBFS_EINVAL, "out of host memory for the batch plan");
     P->count = count;
     P->flags = flags;
     P->ws = (char *)ws;
     P->L = L;
-    if (count == 0) {
-        *plan_out = P;
-        return LEXBFS_OK;
-    }
-    const size_t maxl = dynamic_lds_limit(k_batch<BT>);
-    if (!maxl) {
-        delete P;
-        return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
-    }
-    const size_t region = maxn_wave > 0 ? batch_region_bytes(maxn_wave, kWave) : 0;
-    size_t lds = std::max(batch_region_bytes(std::max(maxn_block, 1), BT), region * (BT / kWave));
-    if (tuning && tuning->lds_bytes > 0) lds = std::max(lds, (size_t)tuning->lds_bytes);
-    if (lds > maxl) {
-        delete P;
-        return fail_code(LEXBFS_ETOOBIG, "batch graph state does not fit the workgroup LDS");
-    }
     char *w = (char *)ws;
 
-    // Host plan: descriptors and the longest-first order.
+    // Host plan: descriptors; the order is workgroup-team graphs, then
+    // wavefront-team graphs, then graphs of the 1024-lane tier, each part
+    // longest first.
     P->table.resize(L.failkeys - L.gds);
     GDesc *hd = (GDesc *)P->table.data();
     int32_t *hsorted = (int32_t *)(P->table.data() + (L.sorted - L.gds));
@@ -1034,23 +1102,48 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
         aoff += a;
         d.lnbuf = (int32_t *)(w + aoff);
         aoff += a;
-        d.failkey = (uint32_t *)(w + L.failkeys) + i;
         d.gtab = nullptr;
+        if (batch_arrays(g.n) == 10) {
+            d.gtab = (uint32_t *)(w + aoff);
+            aoff += 2 * a;
+        }
+        d.failkey = (uint32_t *)(w + L.failkeys) + i;
         d.res = res + i;
         hsorted[i] = i;
     }
-    std::stable_sort(hsorted, hsorted + count, [&](int a, int b) { return gs[a].n > gs[b].n; });
-    int nbig = 0;
-    while (nbig < count && gs[hsorted[nbig]].n > wave_max_n) ++nbig;
+    auto tier = [&](int i) { return gs[i].n > tier_max ? 2 : gs[i].n > wave_max_n ? 0 : 1; };
+    std::stable_sort(hsorted, hsorted + count, [&](int a, int b) {
+        const int ta = tier(a), tb = tier(b);
+        return ta != tb ? ta < tb : gs[a].n > gs[b].n;
+    });
+    int nbig = 0, nsmall = 0;
+    for (int k = 0; k < count; ++k) {
+        const int t = tier(hsorted[k]);
+        nbig += t == 0;
+        nsmall += t == 1;
+    }
+    P->nbig = nbig;
+    P->nsmall = nsmall;
+    P->nlarge = count - nbig - nsmall;
+    P->lds = lds;
+    P->lds_large = maxl_large;
+    P->region = (int)region;
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
-    P->nbig = nbig;
-    P->lds = lds;
-    P->region = (int)region;
-    P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (count - nbig + 3) / 4)));
+    P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (nsmall + 3) / 4)));
+    if (P->nlarge > 0 && side_stream) {
+        // The 1024-lane tier runs on a stream of the plan, forked from and
+        // joined back into the caller's stream at every launch.
+        if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess) {
+            delete P;
+            return fail_code(LEXBFS_EHIP, "creating the batch plan's stream and events");
+        }
+    }
     const hipError_t e =
         hipMemcpyAsync(w + L.gds, P->table.data(), P->table.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e != hipSuccess) {
@@ -1059,6 +1152,14 @@ int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexb
     }
     *plan_out = P;
     return LEXBFS_OK;
+}
+}  // namespace
+
+int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
+                             lexbfs_result_t *res, const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes,
+                             uint32_t flags, void *stream, lexbfs_batch_plan_t **plan_out)
+{
+    return plan_create(gs, count, outs, res, tuning, ws, ws_bytes, flags, stream, true, plan_out);
 }
 
 int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
@@ -1069,18 +1170,42 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
     hipStream_t s = (hipStream_t)stream;
     char *w = P->ws;
     const GDesc *dg = (const GDesc *)(w + P->L.gds);
+    const int32_t *sorted = (const int32_t *)(w + P->L.sorted);
     uint32_t *qctr = (uint32_t *)(w + P->L.qctr);
     {
         ProfScope ps(3, s);
         hipLaunchKernelGGL(k_batch_init, dim3((P->count + 255) / 256), dim3(256), 0, s, dg, P->count, qctr);
     }
     LX_CHECK_LAUNCH("batch init launch");
-    {
+    if (P->nlarge > 0) {
+        hipStream_t ls = s;
+        if (P->side) {
+            hipError_t e = hipEventRecord(P->fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(P->side, P->fork, 0);
+            if (e != hipSuccess) return fail_hip(e, "forking the large-graph stream");
+            ls = P->side;
+        }
+        {
+            ProfScope ps(0, ls);
+            hipLaunchKernelGGL(k_batch_large, dim3(P->nlarge), dim3(kLargeThreads), P->lds_large, ls, dg,
+                               sorted + P->nbig + P->nsmall, P->flags, (int)P->lds_large);
+        }
+        LX_CHECK_LAUNCH("batch large-graph launch");
+        if (P->side) {
+            const hipError_t e = hipEventRecord(P->join, P->side);
+            if (e != hipSuccess) return fail_hip(e, "recording the large-graph join");
+        }
+    }
+    if (P->nbig + P->nsmall > 0) {
         ProfScope ps(0, s);
-        hipLaunchKernelGGL((k_batch<BT>), dim3(P->blocks), dim3(BT), P->lds, s, dg,
-                           (const int32_t *)(w + P->L.sorted), P->nbig, P->count, qctr, P->region, P->flags);
+        hipLaunchKernelGGL((k_batch<BT>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted, P->nbig,
+                           P->nbig + P->nsmall, qctr, P->region, P->flags);
     }
     LX_CHECK_LAUNCH("batch launch");
+    if (P->nlarge > 0 && P->side) {
+        const hipError_t e = hipStreamWaitEvent(s, P->join, 0);
+        if (e != hipSuccess) return fail_hip(e, "joining the large-graph stream");
+    }
     return LEXBFS_OK;
 }
 
@@ -1088,16 +1213,9 @@ void lexbfs_batch_plan_destroy(lexbfs_batch_plan_t *plan) { delete plan; }
 
 int32_t lexbfs_batch_max_n(void)
 {
-    constexpr int BT = kBatchThreads;
-    const size_t lim = dynamic_lds_limit(k_batch<BT>);
+    const size_t lim = dynamic_lds_limit(k_batch<kBatchThreads>);
     if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
-    int lo = 0, hi = 64 * BT;  // largest n in [lo, hi] whose team state fits
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (batch_region_bytes(mid, BT) <= lim) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    return batch_tier_max_n(lim);
 }
 
 int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
@@ -1106,7 +1224,7 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
 {
     if (count == 0 && count >= 0) return LEXBFS_OK;
     lexbfs_batch_plan_t *P = nullptr;
-    int rc = lexbfs_batch_plan_create(gs, count, outs, res, tuning, ws, ws_bytes, flags, stream, &P);
+    int rc = plan_create(gs, count, outs, res, tuning, ws, ws_bytes, flags, stream, false, &P);
     if (rc) return rc;
     rc = lexbfs_batch_plan_launch(P, stream);
     lexbfs_batch_plan_destroy(P);

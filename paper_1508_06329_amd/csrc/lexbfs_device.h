@@ -40,14 +40,20 @@
 //   T' & N(x_i) not empty -> x_{i+1} = its smallest id, top = T' & N(x_i);
 //   else T' not empty     -> x_{i+1} = smallest id of T', top = T';
 //   else                  -> the top class is exhausted: its successor C_1
-//                            is the highest live class start (a bitmap of
-//                            class starts is kept in LDS), each lane matches
-//                            its vertices against C_1, and the rule above is
-//                            applied to C_1.
-// The first two cases cost a few bit operations and one 32-bit max per
-// step; only the third touches every vertex of a lane. Both use pre-split
-// information only, so x_{i+1} is known as soon as x_i's row is in, and the
-// load of x_{i+1}'s row is issued before the splits of step i run.
+//                            is the class holding position U - 1, the
+//                            highest class start at or below it (a bitmap
+//                            of class starts is kept in LDS), each lane
+//                            matches its vertices against C_1, and the rule
+//                            above is applied to C_1.
+// Whether x_i empties the top class is known before any reduction: the top
+// class is [s, U] with s the pivot's class, so it empties iff s = U. Every
+// step therefore takes one team reduction, of the selection key (max) and
+// of the candidate class's neighbour count c (sum); the pivot's class for
+// the next step follows without a read: the adjacent part of the candidate
+// class [s', U - 1] moves to [U - c, U - 1]. Only the third case touches
+// every vertex of a lane. All of this uses pre-split information only, so
+// x_{i+1} is known as soon as x_i's row is in, and the load of x_{i+1}'s row
+// is issued before the splits of step i run.
 //
 // A pivot none of whose neighbours is still unnumbered causes no split; a
 // per-vertex count rem[v] of unnumbered neighbours (decremented during the
@@ -219,6 +225,7 @@ struct WaveTeam {
         sync();
         return v;
     }
+    __device__ __forceinline__ uint32_t max_all_lds(uint32_t v, uint32_t *red) const { return max_all(v, red); }
     // Max of v and sum of s over the team at once; the sum is returned in s.
     __device__ __forceinline__ uint32_t max_sum_all(uint32_t v, uint32_t &s, uint32_t *) const
     {
@@ -266,6 +273,17 @@ struct BlockTeam {
         v = wave_max_dpp(v);
         if ((tid & 63) == 0) red[tid >> 6] = v;
         sync();
+        uint32_t r = red[0];
+#pragma unroll
+        for (int k = 1; k < kWaves; ++k) r = max(r, red[k]);
+        return r;
+    }
+    // max_all with a barrier that orders LDS only (no global tables in use).
+    __device__ __forceinline__ uint32_t max_all_lds(uint32_t v, uint32_t *red) const
+    {
+        v = wave_max_dpp(v);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
         uint32_t r = red[0];
 #pragma unroll
         for (int k = 1; k < kWaves; ++k) r = max(r, red[k]);
@@ -332,8 +350,10 @@ struct LdsTables {
     __device__ __forceinline__ uint32_t word(uint32_t c) const { return cnt[c]; }
     __device__ __forceinline__ void clear(uint32_t c) const { cnt[c] = 0u; }
     __device__ __forceinline__ void inc(uint32_t c) const { atomicAdd(&cnt[c], 1u); }
+    __device__ __forceinline__ void add(uint32_t c, uint32_t k) const { atomicAdd(&cnt[c], k); }
     // Count one neighbour as moved; returns the word before.
     __device__ __forceinline__ uint32_t moved(uint32_t c) const { return atomicAdd(&cnt[c], 0x10000u); }
+    __device__ __forceinline__ uint32_t moved_by(uint32_t c, uint32_t k) const { return atomicAdd(&cnt[c], k << 16); }
 };
 
 struct GlobalTables {
@@ -349,9 +369,17 @@ struct GlobalTables {
     {
         __hip_atomic_fetch_add(&cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __device__ __forceinline__ void add(uint32_t c, uint32_t k) const
+    {
+        __hip_atomic_fetch_add(&cnt[c], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ __forceinline__ uint32_t moved(uint32_t c) const
     {
         return __hip_atomic_fetch_add(&cnt[c], 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ uint32_t moved_by(uint32_t c, uint32_t k) const
+    {
+        return __hip_atomic_fetch_add(&cnt[c], k << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
@@ -562,7 +590,16 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     uint32_t xcls = 0;        // the pivot's (post-split) class, derived at selection
     int par = 0;
     int U = n;
-    for (int i = 0; i < n; ++i) {
+    // Class tables in L2: each lane handles its neighbours class by class,
+    // one atomic round trip per class instead of one per neighbour.
+    constexpr bool kGroup = !Tabs::kInLds;
+    // Single graphs: edges with both ends unnumbered. Once none is left, no
+    // later pivot has an unnumbered neighbour, so nothing splits any more and
+    // the team finishes in the tail loop below.
+    uint32_t eu = kPeo ? 1u : (uint32_t)(row_ptr[n] >> 1);
+    bool tail = false;
+    int i = 0;
+    for (; i < n; ++i) {
         U -= 1;
         const uint32_t stop = Tabs::kInLds ? xcls : (uint32_t)cls[x];
         const bool gone = (int)stop == U;  // x was the last member of the top class
@@ -591,14 +628,24 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
 
         // Phase A: count the neighbours of every hit class; record the parent.
         uint32_t C0 = 0;  // class of my first neighbour, reused in phase B
-        for (uint64_t m = nb; m; m &= m - 1) {
-            const int y = (int)wbase + ctz64(m);
-            const uint32_t C = cls[y];
-            if (m == nb) C0 = C;
-            if (kPeo) fp.par[y] = (uint16_t)x;
-            else parent[y] = (int32_t)x;
-            if (kRem) rem[y] = (uint16_t)(rem[y] - 1);
-            tab.inc(C);
+        if (kGroup) {
+            for (uint64_t m = nb; m;) {
+                const uint32_t C = cls[(int)wbase + ctz64(m)];
+                const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
+                for (uint64_t q = g; q; q &= q - 1) parent[(int)wbase + ctz64(q)] = (int32_t)x;
+                tab.add(C, (uint32_t)__popcll(g));
+                m &= ~g;
+            }
+        } else {
+            for (uint64_t m = nb; m; m &= m - 1) {
+                const int y = (int)wbase + ctz64(m);
+                const uint32_t C = cls[y];
+                if (m == nb) C0 = C;
+                if (kPeo) fp.par[y] = (uint16_t)x;
+                else parent[y] = (int32_t)x;
+                if (kRem) rem[y] = (uint16_t)(rem[y] - 1);
+                tab.inc(C);
+            }
         }
         if (i + 1 == n) break;
 
@@ -626,11 +673,17 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             }
             top = chunk_match(cls, um, cand, vbase, sh, K);
         }
-        // One reduction: the selection key (max) and the candidate class's
-        // neighbour count (sum).
-        uint32_t c_adj = (uint32_t)__popcll(top & nb);
-        const uint32_t k = tm.max_sum_all(pick_key(top, nb, wbase), c_adj, red + par * 2 * NW);
+        // One reduction: the selection key (max) and two 16-bit sums packed
+        // in one word -- the candidate class's neighbour count and x's
+        // unnumbered-neighbour count (each at most n - 1 < 2^16).
+        uint32_t sums = (uint32_t)__popcll(top & nb) | ((uint32_t)__popcll(nb) << 16);
+        const uint32_t k = tm.max_sum_all(pick_key(top, nb, wbase), sums, red + par * 2 * NW);
         par ^= 1;
+        const uint32_t c_adj = sums & 0xFFFFu;
+        if (!kPeo) {
+            eu -= sums >> 16;
+            tail = eu == 0u;
+        }
         const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
         const bool adj = (k >> 16) == 2;
         if (adj) top &= nb;  // narrowed to the pivot's neighbours
@@ -645,22 +698,46 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
 
         // Phase B: move the neighbours to the upper part of their class; the
         // last neighbour of a class to leave closes it.
-        for (uint64_t m = nb; m; m &= m - 1) {
-            const int y = (int)wbase + ctz64(m);
-            const uint32_t C = m == nb ? C0 : (uint32_t)cls[y];
-            const uint32_t c = tab.word(C) & 0xFFFFu;  // final neighbour count of C
-            const uint32_t last = tab.last(C);
-            const bool split = c < last - C + 1;
-            const uint32_t nw = last + 1 - c;
-            if (split) {
-                cls[y] = (uint16_t)nw;
-                tab.set_last(nw, last);
-            }
-            if ((tab.moved(C) >> 16) == c - 1) {  // the last one out closes C
-                tab.clear(C);
+        if (kGroup) {
+            for (uint64_t m = nb; m;) {
+                const uint32_t C = cls[(int)wbase + ctz64(m)];
+                const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);
+                const uint32_t cg = (uint32_t)__popcll(g);
+                const uint32_t c = tab.word(C) & 0xFFFFu;
+                const uint32_t last = tab.last(C);
+                const bool split = c < last - C + 1;
+                const uint32_t nw = last + 1 - c;
                 if (split) {
-                    tab.set_last(C, nw - 1);
-                    atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
+                    for (uint64_t q = g; q; q &= q - 1) cls[(int)wbase + ctz64(q)] = (uint16_t)nw;
+                    tab.set_last(nw, last);
+                }
+                if ((tab.moved_by(C, cg) >> 16) + cg == c) {  // the last group out closes C
+                    tab.clear(C);
+                    if (split) {
+                        tab.set_last(C, nw - 1);
+                        atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
+                    }
+                }
+                m &= ~g;
+            }
+        } else {
+            for (uint64_t m = nb; m; m &= m - 1) {
+                const int y = (int)wbase + ctz64(m);
+                const uint32_t C = m == nb ? C0 : (uint32_t)cls[y];
+                const uint32_t c = tab.word(C) & 0xFFFFu;  // final neighbour count of C
+                const uint32_t last = tab.last(C);
+                const bool split = c < last - C + 1;
+                const uint32_t nw = last + 1 - c;
+                if (split) {
+                    cls[y] = (uint16_t)nw;
+                    tab.set_last(nw, last);
+                }
+                if ((tab.moved(C) >> 16) == c - 1) {  // the last one out closes C
+                    tab.clear(C);
+                    if (split) {
+                        tab.set_last(C, nw - 1);
+                        atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
+                    }
                 }
             }
         }
@@ -670,6 +747,52 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         rp = rpn;
         xp = pn;
         xrem = nrem;
+        if (tail) {
+            ++i;
+            break;
+        }
+    }
+    if (!kPeo && tail) {
+        // Tail: every unnumbered vertex is isolated among the unnumbered, so
+        // pivots only walk down the classes (smallest id first). No rows, no
+        // splits, no class tables: one LDS-ordered reduction per step.
+        for (; i < n; ++i) {
+            U -= 1;
+            const uint32_t stop = xcls;
+            const bool gone = (int)stop == U;
+            if (owner && (x >> 6) == (uint32_t)wi) {
+                um &= ~(1ull << (x & 63));
+                top &= ~(1ull << (x & 63));
+            }
+            if (t == 0) {
+                order[i] = (int32_t)x;
+                rank[x] = i;
+            }
+            if (i + 1 == n) break;
+            uint32_t cand = stop;
+            if (gone) {
+                const uint32_t pos = (uint32_t)(U - 1);
+                int w = (int)(pos >> 6);
+                uint64_t sw = starts[w] & (~0ull >> (63 - (pos & 63)));
+                if (!sw && w > 0) sw = starts[--w];
+                if (sw) {
+                    cand = ((uint32_t)w << 6) | (uint32_t)(63 - __builtin_clzll(sw));
+                } else {
+                    uint32_t hi = 0;
+                    for (int w2 = t; w2 < w; w2 += T) {
+                        const uint64_t s2 = starts[w2];
+                        if (s2) hi = max(hi, (uint32_t)((w2 << 6) | (63 - __builtin_clzll(s2))) + 1u);
+                    }
+                    cand = tm.max_all_lds(hi, red + par * 2 * NW) - 1u;
+                    par ^= 1;
+                }
+                top = chunk_match(cls, um, cand, vbase, sh, K);
+            }
+            const uint32_t k = tm.max_all_lds(pick_key(top, 0ull, wbase), red + par * 2 * NW);
+            par ^= 1;
+            xcls = cand;
+            x = 0xFFFFu - (k & 0xFFFFu);
+        }
     }
     if (kPeo) {
         tm.sync();

@@ -9,9 +9,11 @@ streams, so a batch formed while earlier ones still run overlaps them on the
 device. When a launch completes, its requests record their latency
 (completion - arrival) and release their memory, which admits more.
 
-Graphs above the batch kernel's size limit run as single-graph calls on the
-same streams. Every result is a pure function of its own graph, so a request
-gets the same verdict, witness and certificate alone or in any mix.
+Every admitted graph goes into the launch's batch plan; graphs above the
+256-lane tier's size run on their own 1024-lane workgroups inside the same
+launch (on the plan's side stream), concurrently with the rest. Every result
+is a pure function of its own graph, so a request gets the same verdict,
+witness and certificate alone or in any mix.
 
 The admission logic (:class:`AdmissionController`) is plain host code with no
 device dependency; the tests drive it with a fake clock and executor.
@@ -23,22 +25,6 @@ import ctypes
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Deque, Dict, List, Optional, Sequence
-
-_batch_max_n = None
-
-
-def batch_max_n() -> int:
-    """Largest n the batch kernel takes on this device (its per-graph state
-    must fit one workgroup's LDS); larger graphs run as single calls."""
-    global _batch_max_n
-    if _batch_max_n is None:
-        from . import _lib
-
-        v = int(_lib.load().lexbfs_batch_max_n())
-        _lib.check(min(v, 0), "lexbfs_batch_max_n")
-        _batch_max_n = v
-    return _batch_max_n
-
 
 def footprint_bytes(n: int, nnz: int, W: Optional[int] = None) -> int:
     """Device bytes one request holds while admitted: the bitset, the CSR,
@@ -162,9 +148,8 @@ def pin_graph(g):
 
 
 class GpuExecutor:
-    """Uploads admitted graphs on a copy stream and launches them, as one
-    prepared batch plus single-graph calls for graphs above the batch
-    limit, on the next of several compute streams."""
+    """Uploads admitted graphs on a copy stream and launches them as one
+    prepared batch plan on the next of several compute streams."""
 
     def __init__(self, device="cuda", streams: int = 3, outputs: bool = False):
         import torch
@@ -194,37 +179,18 @@ class GpuExecutor:
         return out, ev
 
     def start(self, reqs: Sequence[Request]):
-        from . import BatchPlan, _lib, lexbfs_outputs_t
+        from . import BatchPlan
 
         torch = self.torch
         s = self.streams[self.next]
         self.next = (self.next + 1) % len(self.streams)
         dgs, up = self._upload([r.graph for r in reqs])
         s.wait_event(up)
-        lim = batch_max_n()
-        small = [i for i, g in enumerate(dgs) if g.n <= lim]
-        large = [i for i, g in enumerate(dgs) if g.n > lim]
-        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "small": small, "large": []}
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "large": []}
         with torch.cuda.stream(s):
-            if small:
-                plan = BatchPlan([dgs[i] for i in small], outputs=self.outputs, stream=s)
-                plan.launch(stream=s)
-                handle["plan"] = plan
-            for i in large:
-                g = dgs[i]
-                res = torch.zeros(8, dtype=torch.int32, device=self.dev)
-                outs = lexbfs_outputs_t()
-                tens = {}
-                if self.outputs:
-                    for k in ("order", "rank", "parent", "cycle"):
-                        tens[k] = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.dev)
-                        setattr(outs, k, tens[k].data_ptr())
-                ws = torch.empty(self.lib.lexbfs_workspace_bytes(g.n), dtype=torch.uint8, device=self.dev)
-                d = g.desc()
-                rc = self.lib.chordal_test(ctypes.byref(d), res.data_ptr(), ctypes.byref(outs), ws.data_ptr(),
-                                           ws.numel(), 0, s.cuda_stream)
-                _lib.check(rc, "chordal_test")
-                handle["large"].append((i, res, ws, tens))
+            plan = BatchPlan(dgs, outputs=self.outputs, stream=s)
+            plan.launch(stream=s)
+            handle["plan"] = plan
         ev = torch.cuda.Event()
         ev.record(s)
         handle["event"] = ev
@@ -238,9 +204,8 @@ class GpuExecutor:
 
         reqs = handle["reqs"]
         if handle["plan"] is not None:
-            rs = handle["plan"].results()
-            for j, i in enumerate(handle["small"]):
-                reqs[i].result = rs[j]
+            for r, res in zip(reqs, handle["plan"].results()):
+                r.result = res
             handle["plan"].close()
         for i, res, ws, tens in handle["large"]:
             chordal, wit, clen, fb = _result_from(res.cpu())
@@ -263,7 +228,7 @@ class SerialExecutor(GpuExecutor):
         s = self.streams[0]
         dgs, up = self._upload([r.graph for r in reqs])
         s.wait_event(up)
-        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "small": [], "large": []}
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "large": []}
         for i, g in enumerate(dgs):
             res = torch.zeros(8, dtype=torch.int32, device=self.dev)
             outs = lexbfs_outputs_t()

@@ -310,6 +310,30 @@ def test_batch_size_limit():
     g = gg.plant(gg.subtree(lim - 12, lim // 4, 8, 31), 12, 32)  # exactly the limit
     assert g.n == lim
     check_batch([g, gg.gnp(300, 0.02, 33)], tag="at the size limit")
-    big = gg.from_edges(lim + 1, [(i, i + 1) for i in range(lim)])
-    with pytest.raises(lx.LexbfsError):
-        lx.chordal_test_batch([lx.DeviceGraph.from_host(big, DEV)])
+    # one above: the 1024-lane tier takes it
+    big = gg.from_edges(lim + 1, [(i, i + 1) for i in range(lim)] + [(0, lim)], "C_lim+1")
+    check_batch([big, gg.gnp(200, 0.05, 34)], tag="one above the 256-lane tier")
+
+
+def test_batch_large_tier_with_plan_and_one_shot():
+    graphs = [gg.plant(gg.subtree(20000, 5000, 12, 41), 9, 42),   # compact LDS state
+              gg.gnp(17000, 0.0005, 43),
+              gg.subtree(40000, 10000, 8, 44)]                      # class tables in global memory
+    graphs += gg.config_batch(count=40, lo=32, hi=4096, seed=45)
+    refs = [oracle.chordal_test(g) for g in graphs]
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    say("[parity] batch with the 1024-lane tier, one-shot")
+    rs = lx.chordal_test_batch(dgs, outputs=True)
+    say("[parity] batch with the 1024-lane tier, plan (side stream), two launches")
+    plan = lx.BatchPlan(dgs, outputs=True)
+    plan.launch()
+    plan.launch()
+    torch.cuda.synchronize()
+    rp = plan.results()
+    for g, ref, a, b in zip(graphs, refs, rs, rp):
+        for r in (a, b):
+            assert np.array_equal(r.order.cpu().numpy(), ref.order), g.name
+            assert np.array_equal(r.parent.cpu().numpy(), ref.parent), g.name
+            assert r.chordal == ref.chordal and r.witness == ref.witness, g.name
+            assert r.cycle_list == ref.cycle.tolist(), g.name
+    plan.close()
