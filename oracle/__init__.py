@@ -8,11 +8,14 @@ The arithmetic lives in ``oracle.c`` (plain sequential C, built with gcc):
 
 * :func:`lexbfs`      -- partition-refinement LexBFS (Section 4.2) with the
   smallest-id tie-break; returns order, rank and the parent p(v).
+* :func:`mcs`         -- Maximum Cardinality Search (Section 5.1) with the
+  smallest-id tie-break, by a heap of (label, id) entries.
 * :func:`peo`         -- the parent-based perfect-elimination test
   (Section 5.2 box), every failing vertex and the canonical witness.
 * :func:`certificate` -- the canonical chordless cycle (project rule; its
   parity is pinned by invariants and brute force, not by the paper).
-* :func:`chordal_test` -- all three for one graph.
+* :func:`chordal_test` -- all three for one graph (``ordering="mcs"``: the
+  same test on the MCS order, Theorem 5.2).
 """
 from __future__ import annotations
 
@@ -52,6 +55,8 @@ def _load():
     lib.oracle_certificate.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, i32p, i32p, i32p]
     lib.oracle_chordal_test.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p]
+    lib.oracle_mcs.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p]
+    lib.oracle_chordal_test_mcs.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p]
     _lib = lib
     return lib
 
@@ -106,6 +111,18 @@ def lexbfs(g) -> OrderResult:
     return OrderResult(order[:n], rank[:n], parent[:n])
 
 
+def mcs(g) -> OrderResult:
+    n = g.n
+    rp, ci = _csr(g)
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    rank = np.zeros(max(n, 1), dtype=np.int32)
+    parent = np.zeros(max(n, 1), dtype=np.int32)
+    rc = _load().oracle_mcs(n, _p(rp), _p(ci), _p(order), _p(rank), _p(parent))
+    if rc != 0:
+        raise RuntimeError(f"oracle_mcs failed ({rc})")
+    return OrderResult(order[:n], rank[:n], parent[:n])
+
+
 def peo(g, rank: np.ndarray) -> PeoResult:
     n = g.n
     rp, ci = _csr(g)
@@ -137,7 +154,9 @@ def certificate(g, order, rank, witness, force_fallback: bool = False):
     return cyc[: int(ln[0])].copy(), bool(fb[0])
 
 
-def chordal_test(g) -> TestResult:
+def chordal_test(g, ordering: str = "lexbfs") -> TestResult:
+    if ordering not in ("lexbfs", "mcs"):
+        raise ValueError(f"unknown ordering {ordering!r}")
     n = g.n
     rp, ci = _csr(g)
     m = max(n, 1)
@@ -146,7 +165,8 @@ def chordal_test(g) -> TestResult:
     parent = np.zeros(m, dtype=np.int32)
     cyc = np.zeros(m, dtype=np.int32)
     res = np.zeros(6, dtype=np.int32)
-    rc = _load().oracle_chordal_test(n, _p(rp), _p(ci), _p(order), _p(rank), _p(parent), _p(cyc), _p(res))
+    fn = _load().oracle_chordal_test if ordering == "lexbfs" else _load().oracle_chordal_test_mcs
+    rc = fn(n, _p(rp), _p(ci), _p(order), _p(rank), _p(parent), _p(cyc), _p(res))
     if rc != 0:
         raise RuntimeError(f"oracle_chordal_test failed ({rc})")
     return TestResult(bool(res[0]), (int(res[1]), int(res[2]), int(res[3])), cyc[: int(res[4])].copy(),

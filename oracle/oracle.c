@@ -22,6 +22,12 @@
  *                       elimination order", with the outer loop over x that
  *                       the box omits, "no parent" as -1, and every failing
  *                       vertex recorded (the box stops at the first).
+ *   oracle_mcs          Section 5.1, Maximum Cardinality Search box: the
+ *                       label of a vertex is the number of its numbered
+ *                       neighbours (the box's "label_x = label_x + 1" is
+ *                       read as the neighbour's label, the same reading as
+ *                       for LexBFS), the largest label is taken next, ties
+ *                       to the smallest id; parent = last adjacent pivot.
  *   oracle_certificate  A chordless cycle for a failing graph. The paper has
  *                       no certificate; the rule is a project definition
  *                       (shortest path in G[(V \ N[v*]) + {x*, z*}] with
@@ -343,19 +349,104 @@ done:
 /* ------------------------------------------------------------------------ */
 /* Whole test for one graph                                                  */
 /* ------------------------------------------------------------------------ */
+/* Maximum Cardinality Search                                                */
+/* ------------------------------------------------------------------------ */
+/*
+ * A binary max-heap of (label, id) entries ordered by larger label, then
+ * smaller id. Raising a label pushes a new entry; entries of numbered
+ * vertices or with an outdated label are dropped when they surface. The
+ * heap top is therefore always the unnumbered vertex of largest label and,
+ * among those, smallest id.
+ */
+typedef struct {
+    int32_t label, id;
+} mcs_entry;
+
+static int mcs_before(mcs_entry a, mcs_entry b)
+{
+    return a.label > b.label || (a.label == b.label && a.id < b.id);
+}
+
+static void mcs_push(mcs_entry *h, int64_t *len, mcs_entry e)
+{
+    int64_t i = (*len)++;
+    h[i] = e;
+    while (i > 0) {
+        int64_t up = (i - 1) / 2;
+        if (!mcs_before(h[i], h[up])) break;
+        mcs_entry t = h[i]; h[i] = h[up]; h[up] = t;
+        i = up;
+    }
+}
+
+static mcs_entry mcs_pop(mcs_entry *h, int64_t *len)
+{
+    mcs_entry top = h[0];
+    h[0] = h[--(*len)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, best = i;
+        if (l < *len && mcs_before(h[l], h[best])) best = l;
+        if (r < *len && mcs_before(h[r], h[best])) best = r;
+        if (best == i) break;
+        mcs_entry t = h[i]; h[i] = h[best]; h[best] = t;
+        i = best;
+    }
+    return top;
+}
+
+int oracle_mcs(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+               int32_t *order, int32_t *rank, int32_t *parent)
+{
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    const int64_t cap = (int64_t)n + (int64_t)row_ptr[n] + 1;
+    mcs_entry *h = (mcs_entry *)malloc(sizeof(mcs_entry) * (size_t)cap);
+    int32_t *label = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!h || !label) { free(h); free(label); return -2; }
+    int64_t len = 0;
+    for (int v = 0; v < n; v++) {
+        label[v] = 0; rank[v] = -1; parent[v] = -1;
+        mcs_entry e = {0, v};
+        mcs_push(h, &len, e);
+    }
+    for (int i = 0; i < n; i++) {
+        int x = -1;
+        while (len > 0) {
+            mcs_entry e = mcs_pop(h, &len);
+            if (rank[e.id] < 0 && label[e.id] == e.label) { x = e.id; break; }
+        }
+        if (x < 0) { free(h); free(label); return -3; }  /* cannot happen */
+        order[i] = x;
+        rank[x] = i;
+        for (int j = row_ptr[x]; j < row_ptr[x + 1]; j++) {
+            int y = col_idx[j];
+            if (rank[y] >= 0) continue;
+            label[y] += 1;
+            parent[y] = x;
+            mcs_entry e = {label[y], y};
+            mcs_push(h, &len, e);
+        }
+    }
+    free(h); free(label);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /*
  * result[0] = chordal (1/0), result[1..3] = witness (v*, x*, z*),
  * result[4] = cycle length (0 if chordal), result[5] = fallback used.
  * order/rank/parent: [n]; cycle: [n] (written only if not chordal).
  */
-int oracle_chordal_test(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
-                        int32_t *order, int32_t *rank, int32_t *parent, int32_t *cycle, int32_t *result)
+static int chordal_test_with(int mcs, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             int32_t *order, int32_t *rank, int32_t *parent, int32_t *cycle, int32_t *result)
 {
     for (int i = 0; i < 6; i++) result[i] = 0;
     result[0] = 1; result[1] = result[2] = result[3] = -1;
     if (n < 0) return -1;
     if (n == 0) return 0;
-    int rc = oracle_lexbfs(n, row_ptr, col_idx, order, rank, parent);
+    int rc = mcs ? oracle_mcs(n, row_ptr, col_idx, order, rank, parent)
+                 : oracle_lexbfs(n, row_ptr, col_idx, order, rank, parent);
     if (rc) return rc;
     int32_t *p = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     uint8_t *fail = (uint8_t *)malloc((size_t)n);
@@ -371,4 +462,17 @@ int oracle_chordal_test(int32_t n, const int32_t *row_ptr, const int32_t *col_id
     if (rc) return rc;
     result[4] = len; result[5] = fb;
     return 0;
+}
+
+int oracle_chordal_test(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        int32_t *order, int32_t *rank, int32_t *parent, int32_t *cycle, int32_t *result)
+{
+    return chordal_test_with(0, n, row_ptr, col_idx, order, rank, parent, cycle, result);
+}
+
+/* The same test on the Maximum Cardinality Search order (Theorem 5.2). */
+int oracle_chordal_test_mcs(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                            int32_t *order, int32_t *rank, int32_t *parent, int32_t *cycle, int32_t *result)
+{
+    return chordal_test_with(1, n, row_ptr, col_idx, order, rank, parent, cycle, result);
 }

@@ -48,6 +48,25 @@ def lexbfs_by_labels(n: int, adj: Sequence[Set[int]]) -> List[int]:
     return order
 
 
+def mcs_by_counts(n: int, adj: Sequence[Set[int]]) -> List[int]:
+    """Maximum Cardinality Search straight from its definition: every step
+    recounts, for each unnumbered vertex, its numbered neighbours and takes
+    the largest count (smallest id on ties)."""
+    numbered = [False] * n
+    order = []
+    for _ in range(n):
+        best, best_cnt = None, -1
+        for v in range(n):
+            if numbered[v]:
+                continue
+            cnt = sum(1 for u in adj[v] if numbered[u])
+            if cnt > best_cnt:
+                best, best_cnt = v, cnt
+        numbered[best] = True
+        order.append(best)
+    return order
+
+
 def satisfies_lb(order: Sequence[int], adj: Sequence[Set[int]]) -> bool:
     n = len(order)
     pos = {v: i for i, v in enumerate(order)}

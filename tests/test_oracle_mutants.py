@@ -9,7 +9,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from brute import (all_graphs, random_adj, witness_by_definition, certificate_by_enumeration, chordal_by_holes, is_chordless_cycle, lexbfs_by_labels)
+from brute import (all_graphs, random_adj, witness_by_definition, certificate_by_enumeration, chordal_by_holes, is_chordless_cycle, lexbfs_by_labels, mcs_by_counts)
 from conftest import load_golden
 
 TESTS = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +33,15 @@ MUTANTS = [
      "if (level[u] == l - 1) { pred = u; break; }", "if (level[u] == l - 1) { pred = u; }"),
     ("certificate path allowed through N(v*)",
      "inA[c] = 0;\n    for (int j = row_ptr[c]; j < row_ptr[c + 1]; j++) inA[col_idx[j]] = 0;", "inA[c] = 0;"),
+    ("MCS raises the pivot's label (the box's literal text)",
+     "label[y] += 1;\n            parent[y] = x;\n            mcs_entry e = {label[y], y};",
+     "label[x] += 1;\n            parent[y] = x;\n            mcs_entry e = {label[y], y};"),
+    ("MCS ties to the largest id",
+     "return a.label > b.label || (a.label == b.label && a.id < b.id);",
+     "return a.label > b.label || (a.label == b.label && a.id > b.id);"),
+    ("MCS parent = first adjacent pivot",
+     "            parent[y] = x;\n            mcs_entry e = {label[y], y};",
+     "            if (parent[y] < 0) parent[y] = x;\n            mcs_entry e = {label[y], y};"),
 ]
 
 
@@ -67,6 +76,26 @@ def run_pins():
                         or r.cycle.tolist() != certificate_by_enumeration(n, adj, v, x, z)):
                     fails.append(f"cert n={n} mask={mask}")
                     break
+    for n in (4, 5):
+        for mask, pairs, adj in all_graphs(n):
+            g = gg.from_edges(n, [(a, b) for a in range(n) for b in adj[a] if a < b])
+            try:
+                r = oracle.chordal_test(g, "mcs")
+            except RuntimeError as e:
+                fails.append(f"mcs n={n} mask={mask}: {e}")
+                break
+            if r.order.tolist() != mcs_by_counts(n, adj) or r.chordal != chordal_by_holes(n, adj):
+                fails.append(f"mcs n={n} mask={mask}")
+                break
+            if not r.chordal and tuple(r.witness) != witness_by_definition(r.order.tolist(), adj):
+                fails.append(f"mcs witness n={n} mask={mask}")
+                break
+            m = oracle.mcs(g)
+            latest = [max((u for u in adj[v] if m.rank[u] < m.rank[v]), key=lambda u: m.rank[u], default=-1)
+                      for v in range(n)]
+            if m.parent.tolist() != latest:
+                fails.append(f"mcs parent n={n} mask={mask}")
+                break
     rng = np.random.default_rng(31)
     for trial in range(80):
         n = 8 + trial % 5
