@@ -38,14 +38,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "single-small", "single-large", "split", "serving", "copy"])
+                    choices=["batch", "single-small", "single-large", "split", "serving", "copy", "ingest"])
     ap.add_argument("--serving-pool", type=int, default=192)
-    ap.add_argument("--serving-requests", type=int, default=800)
+    ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--per-graph-sample", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-step", type=int, default=1, help="also time the per-step-launch LexBFS form (single-graph workloads)")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--ordering", default="lexbfs", choices=["lexbfs", "mcs"],
+                    help="vertex order tested: LexBFS (default) or Maximum Cardinality Search")
     return ap.parse_args()
 
 
@@ -155,7 +157,90 @@ def bench_copy(args):
                       "gbs": 2 * nbytes * args.steps / el / 1e9}), flush=True)
 
 
-def cpu_oracle_rate(graphs, seconds, threads):
+def bench_ingest(args):
+    """Device-side ingestion on the split pair (N = 65,536: CSR 98.5 MB,
+    bitset 512 MiB) and the N = 16,384 pair: the bitset builder kernel
+    against the HBM roofline (bitset written + CSR read), and host-to-device
+    ingestion through the CSR (pinned upload + build) against uploading the
+    whole bitset."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1508_06329_amd as lx
+
+    dev = torch.device("cuda:0")
+    graphs = gg.config_worst_steps() + gg.config_single_large()
+    rows = []
+    for g in graphs:
+        rp_h = torch.from_numpy(g.row_ptr).pin_memory()
+        ci_h = torch.from_numpy(g.col_idx).pin_memory()
+        bits_h = torch.from_numpy(g.bits.view("int64")).pin_memory()
+        rp = rp_h.to(dev)
+        ci = ci_h.to(dev)
+        bits = torch.empty(g.n * g.W, dtype=torch.int64, device=dev)
+        lib = lx._lib.load()
+        stream = torch.cuda.current_stream()
+
+        def build():
+            lx._lib.check(lib.lexbfs_build_bitset(g.n, rp.data_ptr(), ci.data_ptr(), bits.data_ptr(), g.W,
+                                                  stream.cuda_stream), "lexbfs_build_bitset")
+
+        for _ in range(max(args.warmup, 1)):
+            build()
+        torch.cuda.synchronize()
+        assert np.array_equal(bits.cpu().numpy().view(np.uint64), g.bits), g.name
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a, b in evs:
+            a.record()
+            build()
+            b.record()
+        torch.cuda.synchronize()
+        kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        nbytes = g.n * 8 * g.W + 4 * (g.n + 1) + 4 * len(g.col_idx)
+
+        def timed(fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3
+
+        def via_csr():
+            rp.copy_(rp_h, non_blocking=True)
+            ci.copy_(ci_h, non_blocking=True)
+            build()
+
+        def via_bitset():
+            rp.copy_(rp_h, non_blocking=True)
+            ci.copy_(ci_h, non_blocking=True)
+            bits.copy_(bits_h, non_blocking=True)
+
+        via_csr(), via_bitset()
+        t_csr = float(np.median([timed(via_csr) for _ in range(args.steps)]))
+        t_bits = float(np.median([timed(via_bitset) for _ in range(args.steps)]))
+        rows.append({"graph": g.name, "n": g.n, "csr_bytes": 4 * (g.n + 1 + len(g.col_idx)),
+                     "bitset_bytes": g.n * 8 * g.W, "build_ms": kms, "build_gbs": nbytes / kms / 1e6,
+                     "build_frac": nbytes / kms / 1e6 / HBM_PEAK_GBS, "ingest_via_csr_ms": t_csr,
+                     "ingest_via_bitset_ms": t_bits})
+        log(f"{g.name}: build {kms:.3f} ms ({nbytes / kms / 1e6:.0f} GB/s); host->device via CSR {t_csr:.2f} ms, "
+            f"via bitset {t_bits:.2f} ms")
+    big = rows[0]
+    print(json.dumps({
+        "metric": "bitsets built per second from a device CSR (device-side ingestion)",
+        "value": 1e3 / big["build_ms"], "unit": "bitsets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": big["build_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "ingest: N=65,536 split graph (the first of the split pair) and the others of the "
+                               "split and N=16,384 pairs", "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": big["build_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": big["build_frac"], "traffic": None, "kernel": "build_bitset",
+                     "algorithmic_bytes_per_launch": big["bitset_bytes"] + big["csr_bytes"]},
+        "graphs": rows,
+    }), flush=True)
+
+
+def cpu_oracle_rate(graphs, seconds, threads, ordering="lexbfs"):
     """The oracle (unchanged) over the workload's graphs in generation order
     on `threads` host threads (ctypes releases the GIL), for about `seconds`
     or 64 passes, whichever ends first."""
@@ -165,7 +250,7 @@ def cpu_oracle_rate(graphs, seconds, threads):
 
     import oracle
 
-    oracle.chordal_test(graphs[0])
+    oracle.chordal_test(graphs[0], ordering)
     counter = itertools.count()
     lock = threading.Lock()
     stats = {"done": 0, "edges": 0}
@@ -178,7 +263,7 @@ def cpu_oracle_rate(graphs, seconds, threads):
             if k >= limit:
                 break
             g = graphs[k % len(graphs)]
-            oracle.chordal_test(g)
+            oracle.chordal_test(g, ordering)
             with lock:
                 stats["done"] += 1
                 stats["edges"] += g.m
@@ -210,6 +295,8 @@ def main():
         return bench_serving(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "ingest":
+        return bench_ingest(args)
     t = time.time()
     if args.workload == "batch":
         graphs = gg.config_batch()
@@ -225,6 +312,9 @@ def main():
         graphs = gg.config_worst_steps()
         wl = {"workload": "single: N=65,536 split graph (K=4,096 clique, 61,440 independent, 64 clique neighbours "
                           "each) and the copy minus one clique edge, seed 0"}
+    order_flag = lx.LEXBFS_FLAG_MCS if args.ordering == "mcs" else 0
+    if args.ordering == "mcs":
+        wl["workload"] += "; vertex order: Maximum Cardinality Search"
     sum_n = sum(g.n for g in graphs)
     sum_m = sum(g.m for g in graphs)
     log(f"generated {len(graphs)} graphs, sum N={sum_n}, sum M={sum_m} in {time.time() - t:.1f}s")
@@ -237,9 +327,9 @@ def main():
     if args.workload == "batch":
         from paper_1508_06329_amd import autotune
 
-        tune = autotune.autotune_batch(dgs, reps=2)
+        tune = autotune.autotune_batch(dgs, reps=2, flags=order_flag)
         log(f"autotuned schedule {tune['tuning']} from {tune['ms']}")
-        plan = lx.BatchPlan(dgs, tuning=tune["tuning"])
+        plan = lx.BatchPlan(dgs, tuning=tune["tuning"], flags=order_flag)
 
         def step():
             plan.launch()
@@ -252,8 +342,8 @@ def main():
 
         def step():
             for i, d in enumerate(descs):
-                rc = lib.chordal_test(ctypes.byref(d), res[i].data_ptr(), None, ws[i].data_ptr(), ws[i].numel(), 0,
-                                      stream.cuda_stream)
+                rc = lib.chordal_test(ctypes.byref(d), res[i].data_ptr(), None, ws[i].data_ptr(), ws[i].numel(),
+                                      order_flag, stream.cuda_stream)
                 lx._lib.check(rc, "chordal_test")
     for _ in range(args.warmup):
         step()
@@ -293,7 +383,7 @@ def main():
 
     # ---------------- per-step launches (single-graph workloads) ----------------
     per_step = None
-    if args.workload != "batch" and args.per_step:
+    if args.workload != "batch" and args.per_step and args.ordering == "lexbfs":
         lib = lx._lib.load()
         import ctypes
 
@@ -335,7 +425,7 @@ def main():
         descs = [g.desc() for g in sample]
 
         def one(d):
-            rc = lib.chordal_test(ctypes.byref(d), res1.data_ptr(), None, ws1.data_ptr(), ws1.numel(), 0,
+            rc = lib.chordal_test(ctypes.byref(d), res1.data_ptr(), None, ws1.data_ptr(), ws1.numel(), order_flag,
                                   stream.cuda_stream)
             lx._lib.check(rc, "chordal_test")
 
@@ -365,7 +455,7 @@ def main():
     if not args.no_cpu_baseline:
         rows = {}
         for threads in sorted({1, args.cpu_threads}):
-            done, edges, cpu_el = cpu_oracle_rate(graphs, args.cpu_seconds, threads)
+            done, edges, cpu_el = cpu_oracle_rate(graphs, args.cpu_seconds, threads, args.ordering)
             rows[threads] = {"value": done / cpu_el, "unit": "tests/s", "cores": threads, "kind": "oracle",
                              "sample": f"{done} graphs of the same workload in generation order ({cpu_el:.1f}s on "
                                        f"{threads} thread(s): partition-refinement LexBFS + parent test + "
@@ -407,9 +497,13 @@ def bench_serving(args):
     """Poisson stream of graphs, N log-uniform on [64, 32768], the 50/25/25
     mix, admitted under a 64 GB device budget. Requests replay a pool of
     distinct graphs (kept in page-locked host memory, uploaded per request).
-    First the capacity (every request queued at t = 0), then offered rates
-    of 0.5x and 0.8x that capacity for the continuous-batching server and
-    for the plain per-graph path (one chordal_test per request, FIFO)."""
+
+    First the capacity of the plain per-graph path (one chordal_test per
+    request, FIFO, every request queued at t = 0). Both servers then get
+    Poisson arrivals at 0.5x and 0.8x that capacity (the comparison at equal
+    load); the continuous-batching server also gets 4x, 16x and 64x, to show
+    where it saturates. `value` is the highest rate the batching server
+    sustains (throughput >= 95% of the offered rate)."""
     import numpy as np
 
     import graphgen as gg
@@ -431,34 +525,39 @@ def bench_serving(args):
     unit_gaps = rng.exponential(1.0, size=R)
     budget = 64 << 30
     serving.serve(graphs[:32], np.zeros(32), budget_bytes=budget)  # warm-up
-    cap = serving.serve(graphs, np.zeros(R), budget_bytes=budget)
-    log(f"capacity: {cap['throughput']:.0f} tests/s")
+    serving.serve(graphs[:8], np.zeros(8), budget_bytes=budget, serial=True)
+    n_serial = min(R, 200)
+    cap = serving.serve(graphs[:n_serial], np.zeros(n_serial), budget_bytes=budget, serial=True)["throughput"]
+    log(f"per-graph capacity: {cap:.1f} tests/s")
+    keys = ("throughput", "p50_ms", "p99_ms", "peak_bytes")
     rows = {}
+
+    def run(name, frac, count, serial):
+        lam = frac * cap
+        arr = np.cumsum(unit_gaps[:count]) / lam
+        out = serving.serve(graphs[:count], arr, budget_bytes=budget, serial=serial)
+        rows[name] = dict({k: out[k] for k in keys}, offered=lam, requests=count)
+        log(f"{name}: offered {lam:.0f}/s -> {out['throughput']:.0f} tests/s, p50 {out['p50_ms']:.2f} ms, "
+            f"p99 {out['p99_ms']:.2f} ms")
+
     for frac in (0.5, 0.8):
-        lam = frac * cap["throughput"]
-        arr = np.cumsum(unit_gaps) / lam
-        out = serving.serve(graphs, arr, budget_bytes=budget)
-        rows[f"batched@{frac}"] = {k: out[k] for k in ("throughput", "p50_ms", "p99_ms", "peak_bytes")}
-        rows[f"batched@{frac}"]["offered"] = lam
-        log(f"batched at {lam:.0f}/s: {out['throughput']:.0f} tests/s p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms")
-    Rs = max(32, R // 4)
-    lam = 0.5 * cap["throughput"]
-    arr = np.cumsum(unit_gaps[:Rs]) / lam
-    out = serving.serve(graphs[:Rs], arr, budget_bytes=budget, serial=True)
-    rows["per_graph@0.5"] = {k: out[k] for k in ("throughput", "p50_ms", "p99_ms", "peak_bytes")}
-    rows["per_graph@0.5"]["offered"] = lam
-    log(f"per-graph at {lam:.0f}/s: {out['throughput']:.0f} tests/s p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms")
+        run(f"per_graph@{frac}x", frac, min(R, 300), True)
+        run(f"batched@{frac}x", frac, min(R, 600), False)
+    for mult in (4, 16, 64):
+        run(f"batched@{mult}x", mult, R, False)
+    sustained = [r["throughput"] for k, r in rows.items() if k.startswith("batched") and
+                 r["throughput"] >= 0.95 * r["offered"]]
+    best = max(sustained) if sustained else max(r["throughput"] for k, r in rows.items() if k.startswith("batched"))
     edges = float(np.mean([g.m for g in graphs]))
-    main_row = rows["batched@0.8"]
     line = {
         "metric": "chordality tests/s and edges/s, batched vs per-graph on 1 MI355X; p50/p99 ms",
-        "value": main_row["throughput"], "unit": "tests/s", "n_gpus": 1, "higher_is_better": True,
+        "value": best, "unit": "tests/s", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals, N log-uniform on [64, 32768], 50/25/25 mix, "
-                               f"{R} requests over a pool of {P} graphs, 64 GB admission budget, seed 0",
+                               f"up to {R} requests drawn from a pool of {P} graphs, 64 GB admission budget, seed 0",
                    "parallelism": "1 GPU"},
-        "capacity_tests_per_s": cap["throughput"], "edges_per_s": main_row["throughput"] * edges,
-        "p50_ms": main_row["p50_ms"], "p99_ms": main_row["p99_ms"], "rates": rows,
+        "per_graph_capacity_tests_per_s": cap, "edges_per_s": best * edges,
+        "p50_ms": rows["batched@0.8x"]["p50_ms"], "p99_ms": rows["batched@0.8x"]["p99_ms"], "rates": rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -63,6 +63,15 @@ extern "C" {
  * memory) instead of the persistent kernel. Same results; a comparison form,
  * slower by the per-launch cost times 3n. Ignored by chordal_test_batch. */
 #define LEXBFS_FLAG_PER_STEP 0x2u
+/* chordal_test and chordal_test_batch: order the vertices by Maximum
+ * Cardinality Search (Section 5.1 box: the label of a vertex is the number
+ * of its numbered neighbours, the largest label is numbered next, smallest
+ * id first) instead of LexBFS, then run the same perfect-elimination test,
+ * witness and certificate on that order (Theorem 5.2: the graph is chordal
+ * iff its MCS order is a perfect elimination order). Outputs order, rank and
+ * parent are those of the MCS order. Not combinable with
+ * LEXBFS_FLAG_PER_STEP (LEXBFS_EINVAL). */
+#define LEXBFS_FLAG_MCS 0x4u
 
 /* One graph. All pointers are device memory. */
 typedef struct lexbfs_graph {
@@ -187,10 +196,11 @@ int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_out
  * once the table has been staged). lexbfs_batch_plan_launch then only
  * launches kernels (no copies, no memsets), so it may be called many times
  * (the graphs' contents may change between launches, their sizes and
- * addresses may not) and may be captured into a hipGraph. If the batch has
- * graphs above lexbfs_batch_max_n(), the plan owns a stream and two events
- * (created here): each launch forks that stream from `stream`, runs those
- * graphs on it concurrently with the rest, and joins it back into `stream`.
+ * addresses may not) and may be captured into a hipGraph. If the batch mixes
+ * graphs above lexbfs_batch_max_n() with smaller ones, the plan owns a
+ * stream and two events (created here): each launch forks that stream from
+ * `stream`, runs the larger graphs on it concurrently with the rest, and
+ * joins it back into `stream`.
  * Results of a launch are valid once `stream` reaches it. The plan is host
  * memory owned by the caller until lexbfs_batch_plan_destroy, which waits for
  * the plan's own stream; the workspace must stay allocated while the plan is
@@ -223,6 +233,23 @@ const char *lexbfs_last_error(void);
 #define LEXBFS_KERNEL_KINDS 4 /* 0 LexBFS, 1 elimination sweep, 2 witness and certificate, 3 batch setup */
 int lexbfs_profile_enable(int on);
 int lexbfs_profile_collect(int32_t *counts, double *ms);
+
+/*
+ * Device-side ingestion (the step before the path: the paper builds its
+ * N x N Adj matrix on the host and copies it, Section 6.3, and reports input
+ * and allocation as most of its total time, Section 7). Builds the packed
+ * bitset of lexbfs_graph_t from the CSR on `stream`: bit u of row v is set
+ * iff u appears in v's CSR row; every word of every row is written,
+ * padding words (beyond ceil(n/64)) as zero.
+ *   row_ptr  DEVICE [n+1], col_idx DEVICE [row_ptr[n]] (ids >= 64 *
+ *            words_per_row are ignored; the CSR contract of lexbfs_graph_t
+ *            makes the result symmetric with a zero diagonal)
+ *   bits     DEVICE [n * words_per_row], written
+ * Errors: LEXBFS_EINVAL (n < 0, null pointer, words_per_row < ceil(n/64) or
+ * > LEXBFS_MAX_N/64), LEXBFS_ETOOBIG (n > LEXBFS_MAX_N), LEXBFS_EHIP.
+ */
+int lexbfs_build_bitset(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, uint64_t *bits,
+                        int64_t words_per_row, void *stream);
 
 /* Largest n a batch graph may have to run on a wavefront or 256-lane team
  * on the current device (its state, about 12 bytes per vertex, must fit one

@@ -14,6 +14,9 @@ The arithmetic lives in ``oracle.c`` (plain sequential C, built with gcc):
   (Section 5.2 box), every failing vertex and the canonical witness.
 * :func:`certificate` -- the canonical chordless cycle (project rule; its
   parity is pinned by invariants and brute force, not by the paper).
+* :func:`bitset_from_csr` -- the packed adjacency bitset from a CSR, by its
+  definition (the input format of Section 6.3, checked against the device
+  builder).
 * :func:`chordal_test` -- all three for one graph (``ordering="mcs"``: the
   same test on the MCS order, Theorem 5.2).
 """
@@ -121,6 +124,17 @@ def mcs(g) -> OrderResult:
     if rc != 0:
         raise RuntimeError(f"oracle_mcs failed ({rc})")
     return OrderResult(order[:n], rank[:n], parent[:n])
+
+
+def bitset_from_csr(n: int, row_ptr: np.ndarray, col_idx: np.ndarray, words_per_row: int) -> np.ndarray:
+    """The packed adjacency bitset by its definition: bit u (word u // 64,
+    bit u % 64) of row v is set iff u is in v's CSR row; uint64[n, W]."""
+    bits = np.zeros((n, words_per_row), dtype=np.uint64)
+    rows = np.repeat(np.arange(n), np.diff(np.asarray(row_ptr[: n + 1], dtype=np.int64)))
+    cols = np.asarray(col_idx[: len(rows)], dtype=np.int64)
+    keep = cols < 64 * words_per_row
+    np.bitwise_or.at(bits, (rows[keep], cols[keep] // 64), np.left_shift(np.uint64(1), (cols[keep] % 64).astype(np.uint64)))
+    return bits
 
 
 def peo(g, rank: np.ndarray) -> PeoResult:

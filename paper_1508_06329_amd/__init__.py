@@ -15,12 +15,12 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_PER_STEP, LEXBFS_MAX_N, LexbfsError, lexbfs_graph_t, lexbfs_outputs_t,
+from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_MCS, LEXBFS_FLAG_PER_STEP, LEXBFS_MAX_N, LexbfsError, lexbfs_graph_t, lexbfs_outputs_t,
                    lexbfs_result_t, lexbfs_tuning_t)
 
-__all__ = ["BatchPlan", "pack_graphs", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
+__all__ = ["BatchPlan", "pack_graphs", "build_bitset", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
            "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK",
-           "LEXBFS_FLAG_PER_STEP"]
+           "LEXBFS_FLAG_PER_STEP", "LEXBFS_FLAG_MCS"]
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -50,6 +50,15 @@ class DeviceGraph:
             ci = torch.zeros(1, dtype=torch.int32, device=device)[:0]
         bits = torch.from_numpy(g.bits.view("int64")).to(device)
         return cls(g.n, g.W, rp, ci, bits)
+
+    @classmethod
+    def from_csr(cls, n: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, words_per_row: Optional[int] = None,
+                 stream=None) -> "DeviceGraph":
+        """From a device-resident CSR: the bitset is built on the device
+        (lexbfs_build_bitset), so only the CSR has to cross PCIe."""
+        W = int(words_per_row) if words_per_row is not None else (n + 63) // 64
+        bits = build_bitset(n, row_ptr, col_idx, W, stream)
+        return cls(n, W, row_ptr, col_idx, bits)
 
     def desc(self) -> lexbfs_graph_t:
         d = lexbfs_graph_t()
@@ -110,6 +119,19 @@ class KernelTimer:
     def __exit__(self, *exc):
         _lib.load().lexbfs_profile_enable(0)
         return False
+
+
+def build_bitset(n: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, words_per_row: Optional[int] = None,
+                 stream=None) -> torch.Tensor:
+    """The n x words_per_row packed adjacency bitset (int64 tensor holding
+    the uint64 words) built on the device from a device CSR."""
+    W = int(words_per_row) if words_per_row is not None else (n + 63) // 64
+    bits = torch.empty(max(n * W, 1), dtype=torch.int64, device=row_ptr.device)
+    if n > 0:
+        rc = _lib.load().lexbfs_build_bitset(n, row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None,
+                                             bits.data_ptr(), W, _stream_handle(stream))
+        _lib.check(rc, "lexbfs_build_bitset")
+    return bits
 
 
 def workspace_bytes(n: int) -> int:

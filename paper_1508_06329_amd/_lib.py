@@ -25,13 +25,14 @@ LEXBFS_ETOOBIG = -5
 LEXBFS_MAX_N = 65536
 LEXBFS_FLAG_FORCE_FALLBACK = 0x1
 LEXBFS_FLAG_PER_STEP = 0x2
+LEXBFS_FLAG_MCS = 0x4
 LEXBFS_KERNEL_KINDS = 4
 KERNEL_KIND_NAMES = ("lexbfs", "sweep", "certificate", "setup")
 
 EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_order", "chordal_test", "lexbfs_batch_workspace_bytes",
             "chordal_test_batch", "lexbfs_batch_plan_create", "lexbfs_batch_plan_launch",
             "lexbfs_batch_plan_destroy", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_profile_enable",
-            "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_abi_version"]
+            "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_build_bitset", "lexbfs_abi_version"]
 
 
 class lexbfs_graph_t(ctypes.Structure):
@@ -110,6 +111,8 @@ def load() -> ctypes.CDLL:
     lib.lexbfs_profile_enable.argtypes = [ctypes.c_int]
     lib.lexbfs_profile_collect.restype = ctypes.c_int
     lib.lexbfs_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.lexbfs_build_bitset.restype = ctypes.c_int
+    lib.lexbfs_build_bitset.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp]
     lib.lexbfs_batch_max_n.restype = ctypes.c_int32
     lib.lexbfs_batch_max_n.argtypes = []
     lib.lexbfs_abi_version.restype = ctypes.c_int

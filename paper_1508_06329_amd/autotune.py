@@ -45,21 +45,22 @@ def time_plan(plan, reps: int, stream) -> float:
 
 
 def autotune_batch(graphs: Sequence, candidates: Sequence[int] = DEFAULT_CANDIDATES, reps: int = 3,
-                   stream: Optional[torch.cuda.Stream] = None, use_cache: bool = True) -> dict:
+                   stream: Optional[torch.cuda.Stream] = None, use_cache: bool = True, flags: int = 0) -> dict:
     """Time the batch launch over `graphs` (DeviceGraphs) for each candidate
     wave threshold and return ``{"tuning": {"wave_max_n": best}, "ms": {candidate: ms}}``.
+    `flags` are the plan's flags (e.g. the MCS ordering).
     Candidates the plan rejects (their wavefront state does not fit LDS)
     are recorded as None."""
     from . import BatchPlan, LexbfsError
 
-    key = (signature(graphs), tuple(candidates))
+    key = (signature(graphs), tuple(candidates), flags)
     if use_cache and key in _cache:
         return _cache[key]
     stream = stream or torch.cuda.current_stream()
     table = {}
     for c in candidates:
         try:
-            plan = BatchPlan(graphs, tuning={"wave_max_n": c}, stream=stream)
+            plan = BatchPlan(graphs, tuning={"wave_max_n": c}, stream=stream, flags=flags)
         except LexbfsError:
             table[c] = None
             continue

@@ -401,6 +401,17 @@ __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
     }
 }
 
+// Maximum Cardinality Search order of one graph (Section 5.1); the same
+// sweep and certificate kernels then test it.
+template <int T>
+__global__ __launch_bounds__(T) void k_mcs_single(GDesc g)
+{
+    extern __shared__ uint64_t lds[];
+    if (threadIdx.x == 0 && g.failkey) *g.failkey = kNoFail;
+    BlockTeam<T, false> tm{(int)threadIdx.x};
+    mcs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_mcs(lds, g.n, T, false, nullptr));
+}
+
 __global__ __launch_bounds__(kSweepThreads) void k_sweep_single(GDesc g, int rows_per_block, int G, int lg)
 {
     const int r0 = blockIdx.x * rows_per_block;
@@ -532,20 +543,63 @@ __global__ __launch_bounds__(kStepThreads) void k_step_close(GDesc g, StepTabs s
 // One graph of a batch on one team, start to finish: LexBFS with the fused
 // elimination test, then (for a failing graph) the witness and certificate,
 // reusing the team's LDS region.
-template <class Team>
+template <class Team, bool kMcs>
 __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32_t flags)
 {
-    BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
-    lexbfs_team<Team, LdsTables<true>, true>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, B.L.starts,
-                                              B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
+    if (kMcs) {
+        mcs_team<Team, true>(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent,
+                             carve_mcs(region, g.n, Team::kSize, true, g.failkey));
+    } else {
+        BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
+        lexbfs_team<Team, LdsTables<true>, true>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, B.L.starts,
+                                                  B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
+    }
     tm.sync_agent();  // order, rank, parent and the failing rank visible to the team
     finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
     tm.sync();        // the region is reused by the team's next graph
 }
 
+// ---------------------------------------------------------------------------
+// Device-side ingestion: the packed adjacency bitset from the CSR (the
+// paper's Adj matrix, Section 6.3, built on the device instead of copied).
+// One wavefront per row: it clears its row's words in LDS, ORs in the bits
+// of the row's CSR entries (read 64 at a time, coalesced), and writes the
+// row back with coalesced 64-bit stores, padding words included.
+// ---------------------------------------------------------------------------
+constexpr int kBuildThreads = 256;
+
+__global__ __launch_bounds__(kBuildThreads) void k_build_bitset(int n, const int32_t *__restrict__ rp_,
+                                                                const int32_t *__restrict__ ci_, uint64_t *bits_,
+                                                                int64_t W)
+{
+    extern __shared__ uint64_t lds[];
+    LX_GLOBAL const int32_t *rp = as_global(rp_);
+    LX_GLOBAL const int32_t *ci = as_global(ci_);
+    LX_GLOBAL uint64_t *bits = as_global(bits_);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t *row = lds + (int64_t)wave * W;
+    const int64_t lim = W << 6;  // ids beyond the row's words are ignored
+    const int stride = gridDim.x * (kBuildThreads / kWave);
+    for (int v = blockIdx.x * (kBuildThreads / kWave) + wave; v < n; v += stride) {
+        for (int64_t w = lane; w < W; w += kWave) row[w] = 0ull;
+        __builtin_amdgcn_wave_barrier();
+        const int b = rp[v], e = rp[v + 1];
+        for (int j = b + lane; j < e; j += kWave) {
+            const int u = ci[j];
+            if ((unsigned)u < (uint64_t)lim) atomicOr((unsigned long long *)&row[u >> 6], 1ull << (u & 63));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        LX_GLOBAL uint64_t *out = bits + (int64_t)v * W;
+        for (int64_t w = lane; w < W; w += kWave) out[w] = row[w];
+        __builtin_amdgcn_wave_barrier();  // the row buffer is cleared again only after every lane read it
+    }
+}
+
 // Batch: every block first takes large graphs (whole block per graph) from a
 // longest-first queue; once those run out every wave takes small graphs.
-template <int BT>
+template <int BT, bool kMcs>
 __global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, const int32_t *__restrict__ sorted,
                                               int nbig, int count, uint32_t *qctr, int wave_region_bytes,
                                               uint32_t flags)
@@ -559,7 +613,7 @@ __global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, con
         __syncthreads();
         if (k >= nbig) break;
         BlockTeam<BT, false> tm{(int)threadIdx.x};
-        batch_graph(tm, gds[sorted[k]], lds, flags);
+        batch_graph<BlockTeam<BT, false>, kMcs>(tm, gds[sorted[k]], lds, flags);
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     void *region = (char *)lds + (size_t)wave * wave_region_bytes;
@@ -570,7 +624,7 @@ __global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, con
         k = __shfl(k, 0, kWave);
         if (k >= nsmall) break;
         WaveTeam tm{lane};
-        batch_graph(tm, gds[sorted[nbig + k]], region, flags);
+        batch_graph<WaveTeam, kMcs>(tm, gds[sorted[nbig + k]], region, flags);
     }
 }
 
@@ -590,6 +644,7 @@ __global__ void k_batch_init(const GDesc *__restrict__ gds, int count, uint32_t 
 // sweep and certificate on the same workgroup.
 constexpr int kLargeThreads = 1024;
 
+template <bool kMcs>
 __global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__restrict__ gds,
                                                                const int32_t *__restrict__ which, uint32_t flags,
                                                                int lds_limit)
@@ -597,7 +652,10 @@ __global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__re
     extern __shared__ uint64_t lds[];
     constexpr int T = kLargeThreads;
     const GDesc g = gds[which[blockIdx.x]];
-    if (lds_bytes_compact(g.n, T) <= (size_t)lds_limit) {
+    if (kMcs) {
+        BlockTeam<T, false> tm{(int)threadIdx.x};
+        mcs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_mcs(lds, g.n, T, false, nullptr));
+    } else if (lds_bytes_compact(g.n, T) <= (size_t)lds_limit) {
         BlockTeam<T, false> tm{(int)threadIdx.x};
         lexbfs_team_compact(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_compact(lds, g.n, T));
     } else {
@@ -650,23 +708,28 @@ int device_max_lds()
 template <class K>
 size_t dynamic_lds_limit(K kernel)
 {
-    static size_t limit = 0;  // one cache per kernel instantiation
-    if (limit) return limit;
+    // One entry per kernel (not per kernel signature): kernels of one
+    // signature differ in their static LDS and each needs its attribute.
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, size_t>> cache;
+    const void *key = (const void *)kernel;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto &e : cache)
+        if (e.first == key) return e.second;
     const int maxl = device_max_lds();
     if (maxl <= 0) return 0;
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, (const void *)kernel) != hipSuccess) {
+    if (hipFuncGetAttributes(&fa, key) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     const size_t lim = (size_t)maxl - fa.sharedSizeBytes;
-    if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
-        hipSuccess) {
+    if (hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
-    limit = lim;
-    return limit;
+    cache.emplace_back(key, lim);
+    return lim;
 }
 
 // Team size for one graph on its own: K = ceil(n / T) vertices per lane.
@@ -756,6 +819,30 @@ int launch_lexbfs_single(const GDesc &d, hipStream_t s)
         case 256: return launch_lexbfs_single_T<256>(d, s);
         case 512: return launch_lexbfs_single_T<512>(d, s);
         default: return launch_lexbfs_single_T<1024>(d, s);
+    }
+}
+
+template <int T>
+int launch_mcs_single_T(const GDesc &d, hipStream_t s)
+{
+    const size_t lim = dynamic_lds_limit(k_mcs_single<T>);
+    if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the MCS kernel's LDS limit failed");
+    const size_t b = lds_bytes_mcs(d.n, T, false);
+    if (b > lim) return fail_code(LEXBFS_ETOOBIG, "MCS state does not fit the workgroup LDS");
+    ProfScope ps(0, s);
+    hipLaunchKernelGGL(k_mcs_single<T>, dim3(1), dim3(T), b, s, d);
+    LX_CHECK_LAUNCH("MCS launch");
+    return LEXBFS_OK;
+}
+
+int launch_mcs_single(const GDesc &d, hipStream_t s)
+{
+    switch (single_threads(d.n)) {
+        case 64: return launch_mcs_single_T<64>(d, s);
+        case 128: return launch_mcs_single_T<128>(d, s);
+        case 256: return launch_mcs_single_T<256>(d, s);
+        case 512: return launch_mcs_single_T<512>(d, s);
+        default: return launch_mcs_single_T<1024>(d, s);
     }
 }
 
@@ -983,8 +1070,12 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
     hipStream_t s = (hipStream_t)stream;
     const GDesc d = make_desc(g, (char *)ws, L, out ? out->order : nullptr, out ? out->rank : nullptr,
                               out ? out->parent : nullptr, out ? out->cycle : nullptr, res);
+    if ((flags & LEXBFS_FLAG_PER_STEP) && (flags & LEXBFS_FLAG_MCS))
+        return fail_code(LEXBFS_EINVAL, "the per-step form exists for LexBFS only");
     if (g->n > 0) {
-        rc = (flags & LEXBFS_FLAG_PER_STEP) ? launch_lexbfs_per_step(d, s) : launch_lexbfs_single(d, s);
+        rc = (flags & LEXBFS_FLAG_MCS)        ? launch_mcs_single(d, s)
+             : (flags & LEXBFS_FLAG_PER_STEP) ? launch_lexbfs_per_step(d, s)
+                                              : launch_lexbfs_single(d, s);
         if (rc) return rc;
         int G, lg;
         sweep_shape(d.wn, G, lg);
@@ -1036,8 +1127,9 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         *plan_out = P;
         return LEXBFS_OK;
     }
-    const size_t maxl = dynamic_lds_limit(k_batch<BT>);
-    const size_t maxl_large = dynamic_lds_limit(k_batch_large);
+    const bool mcs = (flags & LEXBFS_FLAG_MCS) != 0;
+    const size_t maxl = mcs ? dynamic_lds_limit(k_batch<BT, true>) : dynamic_lds_limit(k_batch<BT, false>);
+    const size_t maxl_large = mcs ? dynamic_lds_limit(k_batch_large<true>) : dynamic_lds_limit(k_batch_large<false>);
     if (!maxl || !maxl_large) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernels' LDS limits failed");
     const int tier_max = batch_tier_max_n(maxl);
     wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
@@ -1134,7 +1226,7 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         cus = 256;
     const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
     P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (nsmall + 3) / 4)));
-    if (P->nlarge > 0 && side_stream) {
+    if (P->nlarge > 0 && nbig + nsmall > 0 && side_stream) {
         // The 1024-lane tier runs on a stream of the plan, forked from and
         // joined back into the caller's stream at every launch.
         if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
@@ -1187,8 +1279,12 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
         }
         {
             ProfScope ps(0, ls);
-            hipLaunchKernelGGL(k_batch_large, dim3(P->nlarge), dim3(kLargeThreads), P->lds_large, ls, dg,
-                               sorted + P->nbig + P->nsmall, P->flags, (int)P->lds_large);
+            if (P->flags & LEXBFS_FLAG_MCS)
+                hipLaunchKernelGGL(k_batch_large<true>, dim3(P->nlarge), dim3(kLargeThreads), P->lds_large, ls, dg,
+                                   sorted + P->nbig + P->nsmall, P->flags, (int)P->lds_large);
+            else
+                hipLaunchKernelGGL(k_batch_large<false>, dim3(P->nlarge), dim3(kLargeThreads), P->lds_large, ls, dg,
+                                   sorted + P->nbig + P->nsmall, P->flags, (int)P->lds_large);
         }
         LX_CHECK_LAUNCH("batch large-graph launch");
         if (P->side) {
@@ -1198,8 +1294,12 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
     }
     if (P->nbig + P->nsmall > 0) {
         ProfScope ps(0, s);
-        hipLaunchKernelGGL((k_batch<BT>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted, P->nbig,
-                           P->nbig + P->nsmall, qctr, P->region, P->flags);
+        if (P->flags & LEXBFS_FLAG_MCS)
+            hipLaunchKernelGGL((k_batch<BT, true>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted, P->nbig,
+                               P->nbig + P->nsmall, qctr, P->region, P->flags);
+        else
+            hipLaunchKernelGGL((k_batch<BT, false>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted, P->nbig,
+                               P->nbig + P->nsmall, qctr, P->region, P->flags);
     }
     LX_CHECK_LAUNCH("batch launch");
     if (P->nlarge > 0 && P->side) {
@@ -1211,9 +1311,32 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
 
 void lexbfs_batch_plan_destroy(lexbfs_batch_plan_t *plan) { delete plan; }
 
+int lexbfs_build_bitset(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, uint64_t *bits,
+                        int64_t words_per_row, void *stream)
+{
+    if (n < 0 || n > LEXBFS_MAX_N) return n < 0 ? LEXBFS_EINVAL : LEXBFS_ETOOBIG;
+    if (n == 0) return LEXBFS_OK;
+    if (!row_ptr || !bits || words_per_row < (n + 63) / 64 || words_per_row > (int64_t)(LEXBFS_MAX_N / 64))
+        return LEXBFS_EINVAL;
+    const size_t lds = (size_t)(kBuildThreads / kWave) * 8 * (size_t)words_per_row;
+    const size_t lim = dynamic_lds_limit(k_build_bitset);
+    if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the bitset builder's LDS limit failed");
+    if (lds > lim) return fail_code(LEXBFS_ETOOBIG, "bitset row buffers do not fit the workgroup LDS");
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int per_block = kBuildThreads / kWave;
+    const int blocks = std::max(1, std::min((n + per_block - 1) / per_block, cus * 8));
+    hipLaunchKernelGGL(k_build_bitset, dim3(blocks), dim3(kBuildThreads), lds, (hipStream_t)stream, n, row_ptr,
+                       col_idx, bits, words_per_row);
+    LX_CHECK_LAUNCH("bitset builder launch");
+    return LEXBFS_OK;
+}
+
 int32_t lexbfs_batch_max_n(void)
 {
-    const size_t lim = dynamic_lds_limit(k_batch<kBatchThreads>);
+    const size_t lim = dynamic_lds_limit(k_batch<kBatchThreads, false>);
     if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
     return batch_tier_max_n(lim);
 }

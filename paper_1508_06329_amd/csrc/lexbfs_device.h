@@ -1054,4 +1054,181 @@ __device__ __forceinline__ void sweep_rows(const uint64_t *bits_, int64_t W, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// Maximum Cardinality Search (Section 5.1): the label of a vertex is the
+// number of its numbered neighbours; each step numbers an unnumbered vertex
+// of largest label, smallest id first (the same tie-break as LexBFS).
+//
+// State: cnt[v] (16 bits, LDS), written only by v's owner lane, so the
+// steps need no class tables and no second barrier. Every lane keeps, as a
+// bitmask over its own vertices, the members of the top bucket (label =
+// cmax, uniform). When x is numbered its unnumbered neighbours gain one:
+//   A = top & N(x) now have cmax + 1  -> the next pivot is min(A) if any;
+//   B = (top \ N(x)) + the neighbours that reach cmax
+//                                     -> else min(B), the top stays cmax;
+//   else no label cmax or cmax + 1 is left: every lane offers its best
+//   (label, -id) and a second reduction finds the new cmax and pivot.
+// One reduction per step (prioritised keys A over B); the parent of y is
+// the last pivot adjacent to y, recorded when its count rises.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline size_t lds_bytes_mcs(int n, int team, bool with_par)
+{
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    const size_t a = align_up(2 * (size_t)n, 16);
+    return align_up(16 * nred, 16) + a + (with_par ? a + 16 : 0);
+}
+
+struct McsLayout {
+    uint32_t *red;
+    uint16_t *cnt;
+    FusedPeo fp;
+};
+
+__device__ __forceinline__ McsLayout carve_mcs(void *base, int n, int team, bool with_par, uint32_t *failkey)
+{
+    const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
+    const size_t a = align_up(2 * (size_t)n, 16);
+    char *p = (char *)base;
+    McsLayout L;
+    L.red = (uint32_t *)p;
+    p += align_up(16 * nred, 16);
+    L.cnt = (uint16_t *)p;
+    p += a;
+    L.fp.par = with_par ? (uint16_t *)p : nullptr;
+    L.fp.fk = with_par ? (uint32_t *)(p + a) : nullptr;
+    L.fp.failkey = failkey;
+    return L;
+}
+
+// Best (label + 1, -id) key over my unnumbered vertices `um` (0 if none),
+// and, for a given label c, the mask of those with that label.
+__device__ __forceinline__ uint32_t mcs_lane_best(const uint16_t *cnt, uint64_t um, int vbase, int sh, int K)
+{
+    uint32_t best = 0;
+    const int wbase = (vbase >> 6) << 6;
+    for (uint64_t m = um; m; m &= m - 1) {
+        const int v = wbase + ctz64(m);
+        const uint32_t c = min((uint32_t)cnt[v] + 1u, 0xFFFFu);
+        best = max(best, (c << 16) | (0xFFFFu - (uint32_t)v));
+    }
+    (void)sh;
+    (void)K;
+    return best;
+}
+
+__device__ __forceinline__ uint64_t mcs_lane_match(const uint16_t *cnt, uint64_t um, uint32_t c, int vbase, int sh, int K)
+{
+    return chunk_match(cnt, um, c, vbase, sh, K);
+}
+
+template <class Team, bool kPeo = false>
+__device__ void mcs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_, int32_t *rank_,
+                         int32_t *parent_, const McsLayout &L)
+{
+    LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
+    LX_GLOBAL int32_t *__restrict__ order = as_global(order_);
+    LX_GLOBAL int32_t *__restrict__ rank = as_global(rank_);
+    LX_GLOBAL int32_t *__restrict__ parent = as_global(parent_);
+    constexpr int T = Team::kSize;
+    constexpr int NW = Team::kWaves;
+    uint16_t *cnt = L.cnt;
+    uint32_t *red = L.red;
+    const FusedPeo &fp = L.fp;
+    const int t = tm.tid;
+    if (n <= 0) return;
+    const int wn = (n + 63) >> 6;
+    int K = 1;
+    while (K * T < n) K <<= 1;
+    const int vbase = t * K;
+    const int wi = vbase >> 6;
+    const int sh = vbase & 63;
+    const uint32_t wbase = (uint32_t)wi << 6;
+    uint64_t cmask = (K == 64) ? ~0ull : (((1ull << K) - 1ull) << sh);
+    if (wi == wn - 1 && (n & 63)) cmask &= (1ull << (n & 63)) - 1ull;
+    const bool owner = vbase < n;
+    LX_GLOBAL const uint64_t *rowbase = bits + wi;
+
+    if (owner)
+        for (int v = vbase; v < min(vbase + K, n); ++v) {
+            cnt[v] = 0;
+            if (kPeo) fp.par[v] = kNoParent;
+            else parent[v] = -1;
+        }
+    if (kPeo && t == 0) *fp.fk = kNoFail;
+    tm.sync();
+
+    uint64_t um = owner ? cmask : 0ull;  // my unnumbered vertices
+    uint64_t top = um;                   // my vertices of label cmax
+    uint32_t cmax = 0;
+    uint32_t x = 0;
+    uint64_t rw = owner ? rowbase[0] : 0ull;
+    uint32_t xp = kNoParent;
+    uint64_t rp = 0ull;
+    int par = 0;
+    for (int i = 0; i < n; ++i) {
+        if (owner && (x >> 6) == (uint32_t)wi) {
+            um &= ~(1ull << (x & 63));
+            top &= ~(1ull << (x & 63));
+        }
+        uint64_t nb = rw & um;
+        uint64_t bad = 0ull;
+        if (kPeo && xp != kNoParent) {
+            bad = rw & ~um & cmask & ~rp;
+            if ((xp >> 6) == (uint32_t)wi) bad &= ~(1ull << (xp & 63));
+        }
+        __asm__ volatile("" : "+v"(nb), "+v"(bad)::"memory");
+        if (kPeo && bad) atomicMin(fp.fk, (uint32_t)i);
+        if (t == 0) {
+            order[i] = (int32_t)x;
+            rank[x] = i;
+        }
+        // Raise my neighbours' labels; those reaching cmax join the top.
+        uint64_t prom = 0ull;
+        for (uint64_t m = nb; m; m &= m - 1) {
+            const int y = (int)wbase + ctz64(m);
+            const uint32_t c = (uint32_t)cnt[y] + 1u;
+            cnt[y] = (uint16_t)c;
+            if (kPeo) fp.par[y] = (uint16_t)x;
+            else parent[y] = (int32_t)x;
+            if (c == cmax) prom |= m & (~m + 1);
+        }
+        if (i + 1 == n) break;
+        const uint64_t A = top & nb;
+        const uint64_t B = (top & ~nb) | prom;
+        uint32_t key = 0;
+        if (A) key = 0x20000u | (0xFFFFu - (wbase + (uint32_t)ctz64(A)));
+        else if (B) key = 0x10000u | (0xFFFFu - (wbase + (uint32_t)ctz64(B)));
+        uint32_t k = tm.max_all(key, red + par * 2 * NW);
+        par ^= 1;
+        if ((k >> 16) == 2) {
+            cmax += 1;
+            top = A;
+        } else if ((k >> 16) == 1) {
+            top = B;
+        } else {
+            k = tm.max_all(mcs_lane_best(cnt, um, vbase, sh, K), red + par * 2 * NW);
+            par ^= 1;
+            cmax = (k >> 16) - 1u;
+            top = mcs_lane_match(cnt, um, cmax, vbase, sh, K);
+        }
+        const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
+        const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
+        const uint64_t rwn = owner ? rowbase[(int64_t)xn * W] : 0ull;
+        const uint64_t rpn = (kPeo && owner && pn != kNoParent) ? rowbase[(int64_t)pn * W] : 0ull;
+        x = xn;
+        rw = rwn;
+        rp = rpn;
+        xp = pn;
+    }
+    if (kPeo) {
+        tm.sync();
+        if (owner)
+            for (int v = vbase; v < min(vbase + K, n); ++v) {
+                const uint32_t p = fp.par[v];
+                parent[v] = p == kNoParent ? -1 : (int32_t)p;
+            }
+        if (t == 0) g_store(fp.failkey, *fp.fk);
+    }
+}
+
 }  // namespace lxd

@@ -90,15 +90,23 @@ class AdmissionController:
 
 
 def run_loop(requests: Sequence[Request], ctrl: AdmissionController, executor, clock: Callable[[], float],
-             idle: Callable[[], None], max_launches: int = 3):
+             idle: Callable[[], None], max_launches=3, classify: Optional[Callable[[Request], object]] = None):
     """Drive arrivals, admission, launches and completions until every
-    request is done or rejected. At most `max_launches` launches run at
-    once (one per compute stream); requests arriving meanwhile queue and
-    are admitted together into the next launch. `executor` provides
-    ``start(requests) -> handle`` (upload + launch, asynchronous),
+    request is done or rejected.
+
+    Admitted requests wait in the queue of their class (``classify(r)``; a
+    single class if None). A class launches all its waiting requests at once
+    whenever fewer than its limit of its launches are running
+    (``max_launches``: an int for every class, or a dict class -> limit), so
+    requests arriving meanwhile are folded into its next launch. `executor`
+    provides ``start(requests[, cls]) -> handle`` (upload + launch,
+    asynchronous; cls passed only when classify is given),
     ``ready(handle) -> bool`` and ``finish(handle)`` (collect results).
     Returns the requests in completion order."""
+    limit = (lambda c: max_launches.get(c, 1)) if isinstance(max_launches, dict) else (lambda c: max_launches)
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    waiting: Dict[object, List[Request]] = collections.defaultdict(list)
+    inflight: Dict[object, int] = collections.defaultdict(int)
     running = []
     finished = []
     total = len(requests)
@@ -106,12 +114,18 @@ def run_loop(requests: Sequence[Request], ctrl: AdmissionController, executor, c
         now = clock()
         while pending and pending[0].arrival <= now:
             ctrl.submit(pending.popleft())
-        adm = ctrl.admit(now) if len(running) < max_launches else []
-        if adm:
-            running.append((executor.start(adm), adm))
-        progressed = bool(adm)
+        progressed = False
+        for r in ctrl.admit(now):
+            waiting[classify(r) if classify else None].append(r)
+        for c, rs in waiting.items():
+            if rs and inflight[c] < limit(c):
+                h = executor.start(rs, c) if classify else executor.start(rs)
+                running.append((h, rs, c))
+                inflight[c] += 1
+                waiting[c] = []
+                progressed = True
         still = []
-        for h, rs in running:
+        for h, rs, c in running:
             if executor.ready(h):
                 executor.finish(h)
                 t = clock()
@@ -119,9 +133,10 @@ def run_loop(requests: Sequence[Request], ctrl: AdmissionController, executor, c
                     r.done = t
                     ctrl.release(r)
                     finished.append(r)
+                inflight[c] -= 1
                 progressed = True
             else:
-                still.append((h, rs))
+                still.append((h, rs, c))
         running = still
         if not progressed:
             idle()
@@ -147,11 +162,19 @@ def pin_graph(g):
             torch.from_numpy(g.bits.view("int64")).pin_memory())
 
 
-class GpuExecutor:
-    """Uploads admitted graphs on a copy stream and launches them as one
-    prepared batch plan on the next of several compute streams."""
+# Requests up to this size form the short class: their launches end within
+# a few milliseconds and never wait for a long graph's chain.
+SHORT_MAX_N = 4096
 
-    def __init__(self, device="cuda", streams: int = 3, outputs: bool = False):
+
+class GpuExecutor:
+    """Uploads admitted graphs on a copy stream and launches each class's
+    batch as one prepared plan on the next of that class's compute streams.
+    Classes: short (n <= SHORT_MAX_N), mid (up to the 256-lane tier's limit)
+    and long (the 1024-lane tier), so a launch lasts only as long as the
+    longest chain of its own class."""
+
+    def __init__(self, device="cuda", streams: Optional[Dict[str, int]] = None, outputs: bool = False):
         import torch
 
         from . import _lib
@@ -160,9 +183,20 @@ class GpuExecutor:
         self.lib = _lib.load()
         self.dev = torch.device(device)
         self.copy = torch.cuda.Stream(device=self.dev)
-        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
-        self.next = 0
+        counts = streams or {"short": 2, "mid": 1, "long": 1}
+        self.streams = {c: [torch.cuda.Stream(device=self.dev) for _ in range(k)] for c, k in counts.items()}
+        self.next = {c: 0 for c in counts}
+        self.launch_limits = dict(counts)
         self.outputs = outputs
+        tier = int(self.lib.lexbfs_batch_max_n())
+        _lib.check(min(tier, 0), "lexbfs_batch_max_n")
+        self.tier_max = tier
+
+    def classify(self, r: Request) -> str:
+        n = r.graph.n
+        if "mid" not in self.streams:
+            return next(iter(self.streams))
+        return "short" if n <= SHORT_MAX_N else "mid" if n <= self.tier_max else "long"
 
     def _upload(self, graphs):
         from . import DeviceGraph
@@ -178,15 +212,16 @@ class GpuExecutor:
         ev.record(self.copy)
         return out, ev
 
-    def start(self, reqs: Sequence[Request]):
+    def start(self, reqs: Sequence[Request], cls: str = "short"):
         from . import BatchPlan
 
         torch = self.torch
-        s = self.streams[self.next]
-        self.next = (self.next + 1) % len(self.streams)
+        group = self.streams[cls]
+        s = group[self.next[cls] % len(group)]
+        self.next[cls] += 1
         dgs, up = self._upload([r.graph for r in reqs])
         s.wait_event(up)
-        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "large": []}
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "singles": []}
         with torch.cuda.stream(s):
             plan = BatchPlan(dgs, outputs=self.outputs, stream=s)
             plan.launch(stream=s)
@@ -207,7 +242,7 @@ class GpuExecutor:
             for r, res in zip(reqs, handle["plan"].results()):
                 r.result = res
             handle["plan"].close()
-        for i, res, ws, tens in handle["large"]:
+        for i, res, ws, tens in handle["singles"]:
             chordal, wit, clen, fb = _result_from(res.cpu())
             n = handle["dgs"][i].n
             reqs[i].result = Result(chordal, wit, clen, fb, **{k: v[:n] for k, v in tens.items()})
@@ -219,16 +254,16 @@ class SerialExecutor(GpuExecutor):
     request, on one stream (admission limited to one in flight)."""
 
     def __init__(self, device="cuda", outputs: bool = False):
-        super().__init__(device, streams=1, outputs=outputs)
+        super().__init__(device, streams={"all": 1}, outputs=outputs)
 
-    def start(self, reqs: Sequence[Request]):
+    def start(self, reqs: Sequence[Request], cls: str = "all"):
         from . import _lib, lexbfs_outputs_t
 
         torch = self.torch
-        s = self.streams[0]
+        s = self.streams["all"][0]
         dgs, up = self._upload([r.graph for r in reqs])
         s.wait_event(up)
-        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "large": []}
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "singles": []}
         for i, g in enumerate(dgs):
             res = torch.zeros(8, dtype=torch.int32, device=self.dev)
             outs = lexbfs_outputs_t()
@@ -242,7 +277,7 @@ class SerialExecutor(GpuExecutor):
             rc = self.lib.chordal_test(ctypes.byref(d), res.data_ptr(), ctypes.byref(outs), ws.data_ptr(),
                                        ws.numel(), 0, s.cuda_stream)
             _lib.check(rc, "chordal_test")
-            handle["large"].append((i, res, ws, tens))
+            handle["singles"].append((i, res, ws, tens))
         ev = torch.cuda.Event()
         ev.record(s)
         handle["event"] = ev
@@ -260,7 +295,8 @@ def serve(graphs: Sequence, arrivals: Sequence[float], budget_bytes: int = 64 <<
     reqs = [Request(i, g, float(a), footprint_bytes(g.n, g.nnz, g.W)) for i, (g, a) in enumerate(zip(graphs, arrivals))]
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0
-    done = run_loop(reqs, ctrl, ex, clock, idle=lambda: time.sleep(20e-6), max_launches=1 if serial else len(ex.streams))
+    done = run_loop(reqs, ctrl, ex, clock, idle=lambda: time.sleep(20e-6), max_launches=ex.launch_limits,
+                    classify=ex.classify)
     wall = clock()
     lat = [r.latency for r in done]
     span = max(r.done for r in done) - min(r.arrival for r in done) if done else float("nan")

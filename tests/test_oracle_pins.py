@@ -302,3 +302,16 @@ def test_random_non_chordal_witness_and_certificate(n, p, seed):
             assert r.cycle.tolist() == certificate_by_enumeration(n, adj, v, x, z)
         assert not r.fallback
     assert seen > 0
+
+
+def test_bitset_from_csr_matches_the_generators_and_a_hand_example():
+    """The oracle's bitset (rebuilt from the CSR) equals the generators' own
+    bitset (built directly, the CSR derived from it), and a 70-vertex hand
+    example crossing a word boundary."""
+    import oracle as orc
+
+    for g in (gg.gnp(300, 0.05, 3), gg.subtree(200, 50, 6, 4), gg.from_edges(130, [(0, 129), (64, 65), (63, 64)])):
+        b = orc.bitset_from_csr(g.n, g.row_ptr, g.col_idx, g.W)
+        assert np.array_equal(b, g.bits.reshape(g.n, g.W)), g.name
+    b = orc.bitset_from_csr(70, np.array([0, 1] + [1] * 68 + [2], dtype=np.int32), np.array([69, 0], dtype=np.int32), 2)
+    assert b[0, 1] == np.uint64(1 << 5) and b[69, 0] == np.uint64(1) and int(b.sum()) == (1 << 5) + 1

@@ -121,3 +121,30 @@ def test_continuous_batching_groups_arrivals():
 def test_percentile():
     xs = list(range(101))
     assert percentile(xs, 50) == 50 and percentile(xs, 99) == 99 and percentile(xs, 0) == 0
+
+
+class ClassExecutor(FakeExecutor):
+    def start(self, reqs, cls):
+        h = super().start(reqs)
+        h["cls"] = cls
+        return h
+
+
+def test_size_classes_do_not_wait_for_each_other():
+    # long requests take 50 ms per launch, short ones 1 ms; with one launch
+    # slot per class, short requests keep flowing while a long launch runs
+    ctrl = AdmissionController(budget_bytes=10 ** 9)
+    clk = FakeClock()
+    ex = ClassExecutor(clk, lambda rs: 5e-2 if rs[0].nbytes > 50 else 1e-3, ctrl)
+    reqs = [Request(i, None, i * 2e-3, 100 if i % 10 == 0 else 1) for i in range(60)]
+    done = run_loop(reqs, ctrl, ex, clk, clk.idle, max_launches={"short": 1, "long": 1},
+                    classify=lambda r: "long" if r.nbytes > 50 else "short")
+    assert len(done) == 60
+    assert all(h["cls"] == ("long" if h["reqs"][0].nbytes > 50 else "short") for h in ex.launches)
+    assert all(len({r.nbytes > 50 for r in h["reqs"]}) == 1 for h in ex.launches)  # no mixed launch
+    short_lat = sorted(r.latency for r in reqs if r.nbytes == 1)
+    assert short_lat[len(short_lat) // 2] < 1e-2  # median short latency far below one long launch
+    # a short launch overlaps a long one
+    spans = [(h["end"] - (5e-2 if h["cls"] == "long" else 1e-3), h["end"], h["cls"]) for h in ex.launches]
+    longs = [sp for sp in spans if sp[2] == "long"]
+    assert any(a[0] < b[0] < a[1] for a in longs for b in spans if b[2] == "short")
