@@ -302,7 +302,8 @@ class BatchPlan:
                 self.tens.append(t)
                 for k, v in t.items():
                     setattr(self.outs_arr[i], k, v.data_ptr())
-        self.res = torch.zeros((max(count, 1), 8), dtype=torch.int32, device=dev)
+        # every launch writes every record, so no clearing kernel is needed
+        self.res = torch.empty((max(count, 1), 8), dtype=torch.int32, device=dev)
         need = int(lib.lexbfs_batch_workspace_bytes(self.arr, count))
         self.ws = _workspace(need, dev)
         tun = None

@@ -196,6 +196,18 @@ __device__ __forceinline__ uint32_t wave_sum_dpp(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Inclusive prefix sum over the 64 lanes (lane order).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_max_dpp(uint32_t v)
 {
     v = dpp_max32_step<0x111, 0xF>(v);  // row_shr:1
@@ -249,6 +261,11 @@ struct WaveTeam {
         return v;
     }
     __device__ __forceinline__ bool any_all(bool p) const { return __ballot(p) != 0ull; }
+    // Exclusive prefix sum over the lanes (lane order = vertex order).
+    __device__ __forceinline__ uint32_t exclusive_scan(uint32_t v, uint32_t *) const
+    {
+        return wave_inclusive_scan(v) - v;
+    }
 };
 
 // On gfx950 a workgroup barrier waits for LDS traffic only; global loads in
@@ -327,6 +344,18 @@ struct BlockTeam {
         return r;
     }
     __device__ __forceinline__ bool any_all(bool p) const { return __syncthreads_or(p) != 0; }
+    // Exclusive prefix sum over the team's lanes in lane order; red: T/64
+    // LDS words, free again after return.
+    __device__ __forceinline__ uint32_t exclusive_scan(uint32_t v, uint32_t *red) const
+    {
+        const uint32_t inc = wave_inclusive_scan(v);
+        if ((tid & 63) == 63) red[tid >> 6] = inc;
+        __syncthreads();
+        uint32_t off = 0;
+        for (int k = 0; k < (tid >> 6); ++k) off += red[k];
+        __syncthreads();
+        return off + inc - v;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -753,45 +782,54 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         }
     }
     if (!kPeo && tail) {
-        // Tail: every unnumbered vertex is isolated among the unnumbered, so
-        // pivots only walk down the classes (smallest id first). No rows, no
-        // splits, no class tables: one LDS-ordered reduction per step.
-        for (; i < n; ++i) {
-            U -= 1;
-            const uint32_t stop = xcls;
-            const bool gone = (int)stop == U;
-            if (owner && (x >> 6) == (uint32_t)wi) {
-                um &= ~(1ull << (x & 63));
-                top &= ~(1ull << (x & 63));
+        // Tail: no unnumbered vertex has an unnumbered neighbour, so nothing
+        // splits any more and the remaining steps only walk down the classes,
+        // smallest id first within a class. With U0 = n - i unnumbered
+        // vertices on positions [0, U0), class C = [C, E - 1] (E the next
+        // class start above C, or U0) is numbered from step i + U0 - E on.
+        // A one-vertex class (E = C + 1) fixes its vertex's rank at once;
+        // every other class is ranked by one team prefix sum over its
+        // members. This is the outcome of the remaining steps, computed
+        // without taking them one by one.
+        const uint32_t U0 = (uint32_t)(n - i);
+        const uint32_t i0 = (uint32_t)i;
+        auto is_start = [&](uint32_t p) { return (starts[p >> 6] >> (p & 63)) & 1ull; };
+        for (uint64_t m = um; m; m &= m - 1) {
+            const int v = (int)wbase + ctz64(m);
+            const uint32_t C = cls[v];
+            if (C + 1u == U0 || is_start(C + 1u)) {
+                const uint32_t r = i0 + U0 - 1u - C;
+                rank[v] = (int32_t)r;
+                order[r] = v;
             }
-            if (t == 0) {
-                order[i] = (int32_t)x;
-                rank[x] = i;
-            }
-            if (i + 1 == n) break;
-            uint32_t cand = stop;
-            if (gone) {
-                const uint32_t pos = (uint32_t)(U - 1);
-                int w = (int)(pos >> 6);
-                uint64_t sw = starts[w] & (~0ull >> (63 - (pos & 63)));
-                if (!sw && w > 0) sw = starts[--w];
-                if (sw) {
-                    cand = ((uint32_t)w << 6) | (uint32_t)(63 - __builtin_clzll(sw));
-                } else {
-                    uint32_t hi = 0;
-                    for (int w2 = t; w2 < w; w2 += T) {
-                        const uint64_t s2 = starts[w2];
-                        if (s2) hi = max(hi, (uint32_t)((w2 << 6) | (63 - __builtin_clzll(s2))) + 1u);
-                    }
-                    cand = tm.max_all_lds(hi, red + par * 2 * NW) - 1u;
-                    par ^= 1;
+        }
+        uint32_t E = U0;  // start of the class above the words still to come
+        for (int w = (int)((U0 - 1u) >> 6); w >= 0; --w) {
+            uint64_t sw = starts[w];
+            if ((uint32_t)w == ((U0 - 1u) >> 6)) sw &= ~0ull >> (63 - ((U0 - 1u) & 63));
+            // A start p heads a one-position class iff p + 1 is a start or
+            // is U0 (a virtual start; inside this word, or the next word's
+            // first position as the carry).
+            const uint64_t carry = E == ((uint32_t)(w + 1) << 6) ? (1ull << 63) : 0ull;
+            const uint64_t virt = sw | ((uint32_t)w == (U0 >> 6) ? (1ull << (U0 & 63)) : 0ull);
+            uint64_t multi = sw & ~((virt >> 1) | carry);  // classes of two or more positions
+            while (multi) {
+                const int b = 63 - __builtin_clzll(multi);
+                multi &= ~(1ull << b);
+                const uint32_t C = ((uint32_t)w << 6) | (uint32_t)b;
+                const uint64_t above = b == 63 ? 0ull : sw & (~0ull << (b + 1));
+                const uint32_t Ec = above ? (((uint32_t)w << 6) | (uint32_t)ctz64(above)) : E;
+                const uint64_t mine = chunk_match(cls, um, C, vbase, sh, K);
+                const uint32_t cnt_l = (uint32_t)__popcll(mine);
+                uint32_t r = i0 + (U0 - Ec) + tm.exclusive_scan(cnt_l, red + par * 2 * NW);
+                for (uint64_t q = mine; q; q &= q - 1) {
+                    const int v = (int)wbase + ctz64(q);
+                    rank[v] = (int32_t)r;
+                    order[r] = v;
+                    ++r;
                 }
-                top = chunk_match(cls, um, cand, vbase, sh, K);
             }
-            const uint32_t k = tm.max_all_lds(pick_key(top, 0ull, wbase), red + par * 2 * NW);
-            par ^= 1;
-            xcls = cand;
-            x = 0xFFFFu - (k & 0xFFFFu);
+            if (sw) E = ((uint32_t)w << 6) | (uint32_t)ctz64(sw);
         }
     }
     if (kPeo) {

@@ -183,7 +183,7 @@ class GpuExecutor:
         self.lib = _lib.load()
         self.dev = torch.device(device)
         self.copy = torch.cuda.Stream(device=self.dev)
-        counts = streams or {"short": 2, "mid": 1, "long": 1}
+        counts = streams or {"short": 1, "mid": 1, "long": 2}
         self.streams = {c: [torch.cuda.Stream(device=self.dev) for _ in range(k)] for c, k in counts.items()}
         self.next = {c: 0 for c in counts}
         self.launch_limits = dict(counts)
@@ -219,13 +219,17 @@ class GpuExecutor:
         group = self.streams[cls]
         s = group[self.next[cls] % len(group)]
         self.next[cls] += 1
-        dgs, up = self._upload([r.graph for r in reqs])
-        s.wait_event(up)
-        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "singles": []}
+        dgs, _ = self._upload([r.graph for r in reqs])
+        # The plan stages its descriptor table on the copy stream, behind the
+        # uploads only, so preparing it never waits for a running launch.
+        with torch.cuda.stream(self.copy):
+            plan = BatchPlan(dgs, outputs=self.outputs, stream=self.copy)
+        ready = torch.cuda.Event()
+        ready.record(self.copy)
+        s.wait_event(ready)
+        handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": plan, "singles": []}
         with torch.cuda.stream(s):
-            plan = BatchPlan(dgs, outputs=self.outputs, stream=s)
             plan.launch(stream=s)
-            handle["plan"] = plan
         ev = torch.cuda.Event()
         ev.record(s)
         handle["event"] = ev
