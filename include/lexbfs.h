@@ -157,7 +157,7 @@ typedef struct lexbfs_tuning {
     int32_t wave_max_n;
     int32_t block_threads;   /* 0 or 256 (the workgroup size); others: LEXBFS_EINVAL */
     int32_t lds_bytes;
-    int32_t reserved;
+    int32_t reserved;        /* must be 0 */
 } lexbfs_tuning_t;
 
 /* Workspace bytes for chordal_test_batch over these graphs (host array). */

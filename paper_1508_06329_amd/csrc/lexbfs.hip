@@ -205,7 +205,7 @@ __device__ int bfs_path(const Team &tm, const GDesc &g, int c, int src, int dst,
             int p = atomicAdd(s_nf, __popcll(f));
             for (; f; f &= f - 1) q[p++] = (w << 6) + ctz64(f);
         }
-        tm.sync_agent();
+        tm.sync_mem();
         const int nf = *s_nf;
         if (nf == 0) return 0;  // dst unreachable
         for (int w = tid; w < wn; w += T) nxt[w] = 0ull;
@@ -240,7 +240,7 @@ __device__ int bfs_path(const Team &tm, const GDesc &g, int c, int src, int dst,
         }
         if (tm.any_all(found)) break;
     }
-    tm.sync_agent();  // levels visible to every lane
+    tm.sync_mem();  // levels visible to every lane
     if (tid == 0) path[d] = dst;
     int y = dst;
     for (int l = d; l >= 1; --l) {
@@ -317,7 +317,7 @@ __device__ void finish_graph(const Team &tm, const GDesc &g, uint32_t flags, con
     const int z = g.order[best];
 
     for (int u = tid; u < g.n; u += T) g.level[u] = 0;  // stamp 0: never matches a search
-    tm.sync_agent();
+    tm.sync_mem();
     int len = 0, fb = 0;
     if (!(flags & LEXBFS_FLAG_FORCE_FALLBACK)) {
         len = bfs_path(tm, g, v, x, z, g.cycle + 1, F, ++stamp);
@@ -350,7 +350,7 @@ __device__ void finish_graph(const Team &tm, const GDesc &g, uint32_t flags, con
                 k += total;
                 tm.sync();
             }
-            tm.sync_agent();
+            tm.sync_mem();
             for (int ia = 0; ia < k && len == 0; ++ia) {
                 const int a = g_load_i(&g.lnbuf[ia]);
                 const uint64_t *rowa = g.bits + (int64_t)a * g.W;
@@ -359,7 +359,7 @@ __device__ void finish_graph(const Team &tm, const GDesc &g, uint32_t flags, con
                     if (test_bit(rowa, b)) continue;
                     if (stamp == 0xFFFFu) {  // stamps exhausted: clear the levels, start over
                         for (int u = tid; u < g.n; u += T) g.level[u] = 0;
-                        tm.sync_agent();
+                        tm.sync_mem();
                         stamp = 0;
                     }
                     len = bfs_path(tm, g, v2, b, a, g.cycle + 1, F, ++stamp);
@@ -399,6 +399,15 @@ __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
         BlockTeam<T, false> tm{(int)threadIdx.x};
         lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
     }
+}
+
+// Parents of a finished order (the global-table LexBFS does not write them
+// during its steps): one wavefront per vertex, grid-stride.
+__global__ __launch_bounds__(256) void k_parents(GDesc g)
+{
+    const int waves = gridDim.x * (256 / kWave);
+    const int first = blockIdx.x * (256 / kWave) + (int)(threadIdx.x >> 6);
+    derive_parents(g.rp, g.ci, g.order, g.rank, g.parent, g.n, first, waves);
 }
 
 // Maximum Cardinality Search order of one graph (Section 5.1); the same
@@ -554,7 +563,7 @@ __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32
         lexbfs_team<Team, LdsTables<true>, true>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, B.L.starts,
                                                   B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
     }
-    tm.sync_agent();  // order, rank, parent and the failing rank visible to the team
+    tm.sync_mem();  // order, rank, parent and the failing rank visible to the team
     finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
     tm.sync();        // the region is reused by the team's next graph
 }
@@ -663,16 +672,18 @@ __global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__re
         GlobalTables tab{g.gtab, g.gtab + g.n};
         BlockTeam<T, true> tm{(int)threadIdx.x};
         lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, nullptr, tab, L.red);
+        tm.sync_mem();  // order and rank visible to every wave
+        derive_parents(g.rp, g.ci, g.order, g.rank, g.parent, g.n, (int)(threadIdx.x >> 6), T / kWave);
     }
     BlockTeam<T, false> tm{(int)threadIdx.x};
-    tm.sync_agent();  // rank and parent of every vertex visible to the sweep
+    tm.sync_mem();  // rank and parent of every vertex visible to the sweep
     int G = 1, lg = 0;
     while (G < g.wn && G < kWave) {
         G <<= 1;
         ++lg;
     }
     sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, 0, g.n, G, lg, g.failkey);
-    tm.sync_agent();  // the failing rank visible to the certificate
+    tm.sync_mem();  // the failing rank visible to the certificate
     finish_graph(tm, g, flags, carve_finish(lds, g.wn, T / kWave));
 }
 
@@ -806,6 +817,9 @@ int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
     } else {
         if (b_g > lim_g) return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
         hipLaunchKernelGGL((k_lexbfs_single<T, kModeGlobal>), dim3(1), dim3(T), b_g, s, d);
+        LX_CHECK_LAUNCH("LexBFS launch");
+        const int blocks = std::min((d.n + 3) / 4, 2048);
+        hipLaunchKernelGGL(k_parents, dim3(blocks), dim3(256), 0, s, d);
     }
     LX_CHECK_LAUNCH("LexBFS launch");
     return LEXBFS_OK;

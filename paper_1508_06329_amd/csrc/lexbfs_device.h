@@ -246,13 +246,16 @@ struct WaveTeam {
         sync();
         return v;
     }
-    // Barrier that also makes global stores of every lane visible to every
-    // lane (agent-scope release and acquire around it).
-    __device__ __forceinline__ void sync_agent() const
+    // Barrier that also orders the team's global memory accesses. A team
+    // is one wavefront (or one workgroup, below) on one CU, and everything
+    // it shares through global memory is written and read inside the team,
+    // so workgroup scope is the right one. Agent scope would compile to an
+    // L2 write-back and invalidate on this multi-XCD part.
+    __device__ __forceinline__ void sync_mem() const
     {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     __device__ __forceinline__ uint32_t min_all(uint32_t v, uint32_t *) const
     {
@@ -270,8 +273,9 @@ struct WaveTeam {
 
 // On gfx950 a workgroup barrier waits for LDS traffic only; global loads in
 // flight (the prefetched pivot row) stay in flight across it. With the class
-// tables in global memory the barrier also orders those accesses (agent
-// fences), which does wait for every outstanding memory operation.
+// tables in global memory (kGlobalTables) every table access is an L2
+// atomic, load or store of this workgroup; the barrier's workgroup-scope
+// release and acquire order them (the waves share one CU's memory path).
 template <int T, bool kGlobalTables>
 struct BlockTeam {
     int tid;
@@ -279,9 +283,9 @@ struct BlockTeam {
     static constexpr int kWaves = T / kWave;
     __device__ __forceinline__ void sync() const
     {
-        if (kGlobalTables) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        if (kGlobalTables) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     // Max over the team (one barrier); every lane gets the result.
     // red: T/64 LDS words, not reused before the next barrier.
@@ -325,11 +329,13 @@ struct BlockTeam {
         s = q;
         return r;
     }
-    __device__ __forceinline__ void sync_agent() const
+    // Barrier that also orders the workgroup's global memory accesses
+    // (see WaveTeam::sync_mem for the scope).
+    __device__ __forceinline__ void sync_mem() const
     {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     // Min over the team; red: T/64 LDS words, free again after return.
     __device__ __forceinline__ uint32_t min_all(uint32_t v, uint32_t *red) const
@@ -579,6 +585,11 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     constexpr int T = Team::kSize;
     constexpr int NW = Team::kWaves;
     constexpr bool kRem = Tabs::kRem;
+    // Class tables in L2: each lane handles its neighbours class by class,
+    // one atomic round trip per class instead of one per neighbour, and the
+    // parents are not written during the steps (a lane may own 64 neighbours
+    // of one pivot); derive_parents computes them from the finished order.
+    constexpr bool kGroup = !Tabs::kInLds;
     const int t = tm.tid;
     if (n <= 0) return;
     const int wn = (n + 63) >> 6;
@@ -601,7 +612,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     }
     for (int w = t; w < wn; w += T) starts[w] = w == 0 ? 1ull : 0ull;  // one class, starting at 0
     // parent[v] is later written only by v's owner lane; the same lane clears it.
-    if (!kPeo && owner)
+    if (!kPeo && !kGroup && owner)
         for (int v = vbase; v < min(vbase + K, n); ++v) parent[v] = -1;
     if (t == 0) {
         tab.set_last(0, (uint32_t)(n - 1));
@@ -619,9 +630,6 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     uint32_t xcls = 0;        // the pivot's (post-split) class, derived at selection
     int par = 0;
     int U = n;
-    // Class tables in L2: each lane handles its neighbours class by class,
-    // one atomic round trip per class instead of one per neighbour.
-    constexpr bool kGroup = !Tabs::kInLds;
     // Single graphs: edges with both ends unnumbered. Once none is left, no
     // later pivot has an unnumbered neighbour, so nothing splits any more and
     // the team finishes in the tail loop below.
@@ -661,8 +669,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             for (uint64_t m = nb; m;) {
                 const uint32_t C = cls[(int)wbase + ctz64(m)];
                 const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
-                for (uint64_t q = g; q; q &= q - 1) parent[(int)wbase + ctz64(q)] = (int32_t)x;
-                tab.add(C, (uint32_t)__popcll(g));
+                tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
                 m &= ~g;
             }
         } else {
@@ -1049,6 +1056,31 @@ __device__ void lexbfs_team_compact(const Team &tm, int n, const uint64_t *bits_
 // a rank lookup. The smallest failing rank is kept with atomicMin.
 // A group of G lanes (a power of two <= 64) handles one row.
 // ---------------------------------------------------------------------------
+// p(v) from a finished order: the neighbour of largest rank below rank(v)
+// (the latest earlier neighbour of Section 5.2), or -1. One wavefront per
+// vertex: its lanes split v's CSR row and a wave max picks the rank.
+// Vertices v = first, first + stride, ...
+__device__ __forceinline__ void derive_parents(const int32_t *row_ptr_, const int32_t *col_idx_, const int32_t *order_,
+                                               const int32_t *rank_, int32_t *parent_, int n, int first, int stride)
+{
+    LX_GLOBAL const int32_t *rp = as_global(row_ptr_);
+    LX_GLOBAL const int32_t *ci = as_global(col_idx_);
+    LX_GLOBAL const int32_t *order = as_global(order_);
+    LX_GLOBAL const int32_t *rank = as_global(rank_);
+    LX_GLOBAL int32_t *parent = as_global(parent_);
+    const int lane = threadIdx.x & 63;
+    for (int v = first; v < n; v += stride) {
+        const int rv = rank[v];
+        uint32_t best = 0;  // rank + 1 of the latest earlier neighbour so far
+        for (int j = rp[v] + lane; j < rp[v + 1]; j += kWave) {
+            const int ru = rank[ci[j]];
+            if (ru < rv) best = max(best, (uint32_t)ru + 1u);
+        }
+        best = wave_max_u32(best);
+        if (lane == 0) parent[v] = best ? order[best - 1] : -1;
+    }
+}
+
 __device__ __forceinline__ void sweep_rows(const uint64_t *bits_, int64_t W, int wn, const int32_t *rank_,
                                            const int32_t *parent_, int n, int r0, int r1, int G, int lg,
                                            uint32_t *failkey_)
