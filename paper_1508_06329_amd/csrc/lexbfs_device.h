@@ -726,10 +726,12 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         // The candidate class spans [cand, U - 1]; its c_adj members adjacent
         // to x move to [U - c_adj, U - 1] and hold the next pivot.
         xcls = adj ? (uint32_t)U - c_adj : cand;
+        // The next pivot's row first (the latency that bounds the step); a
+        // pivot with no unnumbered neighbour may not need it, but asking rem
+        // first would put an LDS round trip in front of the load.
+        const uint64_t rwn = owner ? rowbase[(int64_t)xn * W] : 0ull;
         const bool nrem = !kRem || rem[xn] > 0;
         const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
-        const bool need = nrem || pn != kNoParent;  // the test reads row_v even when it splits nothing
-        const uint64_t rwn = (owner && need) ? rowbase[(int64_t)xn * W] : 0ull;
         const uint64_t rpn = (kPeo && owner && pn != kNoParent) ? rowbase[(int64_t)pn * W] : 0ull;
 
         // Phase B: move the neighbours to the upper part of their class; the
