@@ -240,6 +240,27 @@ def permutation(n: int, seed: int) -> np.ndarray:
 # Workload configurations (seed 0 unless stated).
 # ---------------------------------------------------------------------------
 
+def intervals(n: int, avg_deg: float, seed: int, unit: bool = True) -> Graph:
+    """Intersection graph of n random closed intervals on a line: left ends
+    uniform on [0, 2n / avg_deg), length 1 (unit) or uniform on [0, 2), ids
+    shuffled by a random permutation (so they do not follow the line)."""
+    u = rng_stream(seed, 2 * n).astype(np.float64) / 2.0 ** 64
+    span = 2.0 * n / max(avg_deg, 1e-9)
+    left = u[:n] * span
+    right = left + (1.0 if unit else 2.0 * u[n:])
+    idx = np.argsort(left, kind="stable")
+    edges = []
+    for a in range(n):  # sweep by left end: b intersects a iff left[b] <= right[a]
+        i = idx[a]
+        for b in range(a + 1, n):
+            j = idx[b]
+            if left[j] > right[i]:
+                break
+            edges.append((int(i), int(j)))
+    g = from_edges(n, edges, f"{'unit_' if unit else ''}intervals({n},{avg_deg})")
+    return relabel(g, permutation(n, seed + 1))
+
+
 def config_single_small(seed: int = 0) -> List[Graph]:
     """N = 1,024 subtree graph (host tree 256 nodes, subtree size in [1, 8]),
     and the same graph with a planted chordless 5-cycle (N = 1,029)."""

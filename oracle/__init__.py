@@ -17,6 +17,10 @@ The arithmetic lives in ``oracle.c`` (plain sequential C, built with gcc):
 * :func:`bitset_from_csr` -- the packed adjacency bitset from a CSR, by its
   definition (the input format of Section 6.3, checked against the device
   builder).
+* :func:`lexbfs_plus`, :func:`unit_interval_test` -- multi-sweep LexBFS
+  (ties to the vertex last in the previous order) and the three-sweep test
+  for unit interval graphs (a step towards interval recognition, which the
+  paper names as future work).
 * :func:`chordal_test` -- all three for one graph (``ordering="mcs"``: the
   same test on the MCS order, Theorem 5.2).
 """
@@ -135,6 +139,82 @@ def bitset_from_csr(n: int, row_ptr: np.ndarray, col_idx: np.ndarray, words_per_
     keep = cols < 64 * words_per_row
     np.bitwise_or.at(bits, (rows[keep], cols[keep] // 64), np.left_shift(np.uint64(1), (cols[keep] % 64).astype(np.uint64)))
     return bits
+
+
+def _relabelled_csr(g, new_id: np.ndarray):
+    """CSR of g with vertex v renamed new_id[v], rows ascending."""
+    n = g.n
+    src = np.repeat(np.arange(n), np.diff(np.asarray(g.row_ptr, dtype=np.int64)))
+    a = new_id[src]
+    b = new_id[np.asarray(g.col_idx[: len(src)], dtype=np.int64)]
+    key = np.lexsort((b, a))
+    a, b = a[key], b[key]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, a + 1, 1)
+    return np.cumsum(rp).astype(np.int32), b.astype(np.int32)
+
+
+class _Csr:
+    def __init__(self, n, row_ptr, col_idx):
+        self.n, self.row_ptr, self.col_idx = n, row_ptr, col_idx
+
+
+def lexbfs_plus(g, prev_order: np.ndarray) -> OrderResult:
+    """LexBFS+ (the '+' rule of multi-sweep LexBFS): among the unnumbered
+    vertices of largest label, the one that comes last in prev_order. With
+    new_id(v) = n - 1 - position of v in prev_order, that is the smallest
+    new id, so this runs :func:`lexbfs` on the renamed graph and maps the
+    order back."""
+    n = g.n
+    pos = np.empty(n, dtype=np.int64)
+    pos[np.asarray(prev_order, dtype=np.int64)] = np.arange(n)
+    new_id = n - 1 - pos
+    old_of = np.empty(n, dtype=np.int64)
+    old_of[new_id] = np.arange(n)
+    rp, ci = _relabelled_csr(g, new_id)
+    r = lexbfs(_Csr(n, rp, ci))
+    order = old_of[r.order].astype(np.int32)
+    rank = np.empty(n, dtype=np.int32)
+    rank[order] = np.arange(n, dtype=np.int32)
+    parent = np.where(r.parent[new_id] >= 0, old_of[np.maximum(r.parent[new_id], 0)], -1).astype(np.int32)
+    return OrderResult(order, rank, parent)
+
+
+@dataclass
+class UnitIntervalResult:
+    unit_interval: bool
+    order: np.ndarray   # the third sweep
+    witness: tuple      # (a, b, c): a < b < c in the order, ac an edge, ab or bc not; or (-1, -1, -1)
+
+
+def unit_interval_test(g) -> UnitIntervalResult:
+    """Three sweeps -- LexBFS, then LexBFS+ twice -- and the test that every
+    closed neighbourhood is consecutive in the third order (a unit interval
+    ordering: u < v < w and uw an edge imply uv and vw edges). Witness: the
+    earliest vertex v whose closed neighbourhood is not consecutive, b the
+    earliest non-neighbour between its first and last closed neighbour, and
+    the triple (first, b, v) if b comes before v, else (v, b, last)."""
+    n = g.n
+    s1 = lexbfs(g).order
+    s2 = lexbfs_plus(g, s1).order
+    s3 = lexbfs_plus(g, s2).order
+    pos = np.empty(n, dtype=np.int64)
+    pos[s3] = np.arange(n)
+    for i in range(n):
+        v = int(s3[i])
+        nbrs = g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]
+        ps = np.concatenate([pos[nbrs], [i]])
+        lo, hi = int(ps.min()), int(ps.max())
+        if hi - lo + 1 == len(ps):
+            continue
+        inside = np.zeros(hi - lo + 1, dtype=bool)
+        inside[ps - lo] = True
+        b_pos = lo + int(np.argmin(inside))
+        b = int(s3[b_pos])
+        if b_pos < i:
+            return UnitIntervalResult(False, s3, (int(s3[lo]), b, v))
+        return UnitIntervalResult(False, s3, (v, b, int(s3[hi])))
+    return UnitIntervalResult(True, s3, (-1, -1, -1))
 
 
 def peo(g, rank: np.ndarray) -> PeoResult:

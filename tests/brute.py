@@ -48,6 +48,52 @@ def lexbfs_by_labels(n: int, adj: Sequence[Set[int]]) -> List[int]:
     return order
 
 
+def lexbfs_plus_by_labels(n: int, adj: Sequence[Set[int]], prev: Sequence[int]) -> List[int]:
+    """LexBFS with literal label strings, ties to the vertex that comes last
+    in the previous order `prev` (the '+' rule)."""
+    pos = {v: i for i, v in enumerate(prev)}
+    label = [[] for _ in range(n)]
+    numbered = [False] * n
+    order = []
+    for i in range(1, n + 1):
+        best = None
+        for v in range(n):
+            if numbered[v]:
+                continue
+            if best is None or label[v] > label[best] or (label[v] == label[best] and pos[v] > pos[best]):
+                best = v
+        numbered[best] = True
+        order.append(best)
+        for y in adj[best]:
+            if not numbered[y]:
+                label[y] = label[y] + [n - i]
+    return order
+
+
+def closed_nbhds_consecutive(order: Sequence[int], adj: Sequence[Set[int]]) -> bool:
+    pos = {v: i for i, v in enumerate(order)}
+    for v in order:
+        ps = [pos[u] for u in adj[v]] + [pos[v]]
+        if max(ps) - min(ps) + 1 != len(ps):
+            return False
+    return True
+
+
+def unit_interval_by_orderings(n: int, adj: Sequence[Set[int]]) -> bool:
+    """Unit (proper) interval graph iff some vertex order makes every closed
+    neighbourhood consecutive (Roberts); tried over all orders."""
+    return any(closed_nbhds_consecutive(p, adj) for p in itertools.permutations(range(n)))
+
+
+def has_induced_claw(n: int, adj: Sequence[Set[int]]) -> bool:
+    for c in range(n):
+        nb = sorted(adj[c])
+        for a, b, d in itertools.combinations(nb, 3):
+            if b not in adj[a] and d not in adj[a] and d not in adj[b]:
+                return True
+    return False
+
+
 def mcs_by_counts(n: int, adj: Sequence[Set[int]]) -> List[int]:
     """Maximum Cardinality Search straight from its definition: every step
     recounts, for each unnumbered vertex, its numbered neighbours and takes

@@ -139,3 +139,52 @@ def test_mutant_is_caught(tmp_path, idx):
             "    sys.exit(1 if t.run_pins() else 0)\n") % (ROOT, TESTS, so)
     proc = subprocess.run([sys.executable, "-c", code], capture_output=True, timeout=300)
     assert proc.returncode != 0, f"pins did not catch: {name}"
+
+
+# Planted mistakes in the Python part of the oracle (multi-sweep LexBFS+ and
+# the unit interval test), each in a copy of the package run in a child
+# process against the interval pins.
+PY_MUTANTS = [
+    ("LexBFS+ ties to the first instead of the last vertex of the previous order",
+     "    new_id = n - 1 - pos\n", "    new_id = pos.copy()\n"),
+    ("open instead of closed neighbourhoods",
+     "        ps = np.concatenate([pos[nbrs], [i]])\n", "        ps = pos[nbrs] if len(nbrs) else np.array([i])\n"),
+    ("two sweeps instead of three",
+     "    s3 = lexbfs_plus(g, s2).order\n", "    s3 = s2\n"),
+]
+
+
+@pytest.mark.parametrize("idx", range(len(PY_MUTANTS)))
+def test_python_mutant_is_caught(tmp_path, idx):
+    import shutil
+
+    name, old, new = PY_MUTANTS[idx]
+    pkg = os.path.dirname(oracle.__file__)
+    dst = tmp_path / "oracle"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("__pycache__"))
+    src = (dst / "__init__.py").read_text()
+    assert src.count(old) == 1, f"mutation site not found: {name}"
+    (dst / "__init__.py").write_text(src.replace(old, new))
+    code = ("import sys; sys.path[:0] = [%r, %r, %r]\n"
+            "import oracle\n"
+            "assert oracle.__file__.startswith(%r)\n"
+            "import test_oracle_interval as t, pytest\n"
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', t.__file__]))\n") % (
+        str(tmp_path), ROOT, TESTS, str(tmp_path))
+    proc = subprocess.run([sys.executable, "-c", code], capture_output=True, timeout=600, cwd=str(tmp_path))
+    assert proc.returncode != 0, f"pins did not catch: {name}"
+
+
+def test_python_unmutated_copy_passes(tmp_path):
+    import shutil
+
+    pkg = os.path.dirname(oracle.__file__)
+    shutil.copytree(pkg, tmp_path / "oracle", ignore=shutil.ignore_patterns("__pycache__"))
+    code = ("import sys; sys.path[:0] = [%r, %r, %r]\n"
+            "import oracle\n"
+            "assert oracle.__file__.startswith(%r)\n"
+            "import test_oracle_interval as t, pytest\n"
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', t.__file__]))\n") % (
+        str(tmp_path), ROOT, TESTS, str(tmp_path))
+    proc = subprocess.run([sys.executable, "-c", code], capture_output=True, timeout=600, cwd=str(tmp_path))
+    assert proc.returncode == 0, proc.stdout.decode()[-2000:] + proc.stderr.decode()[-2000:]
