@@ -14,7 +14,8 @@ timed steps. The per-graph path (one chordal_test call per graph) is timed
 on an evenly spaced sample of the same graphs, and the CPU oracle on a
 bounded sample on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch|single-small|single-large|split|serving|copy]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                      [--workload batch|single-small|single-large|split|serving|copy|ingest|interval]
 """
 import argparse
 import json
@@ -38,7 +39,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "single-small", "single-large", "split", "serving", "copy", "ingest"])
+                    choices=["batch", "single-small", "single-large", "split", "serving", "copy", "ingest", "interval"])
     ap.add_argument("--serving-pool", type=int, default=192)
     ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--per-graph-sample", type=int, default=512)
@@ -240,6 +241,102 @@ def bench_ingest(args):
     }), flush=True)
 
 
+def bench_interval(args):
+    """Three-sweep unit interval test (LexBFS, LexBFS+, LexBFS+, then the
+    consecutive-neighbourhood check) on N = 16,384 interval graphs of unit
+    and of mixed lengths and an N = 65,536 unit interval graph (average
+    degree 16, 16 and 12; ids shuffled). A step is one unit_interval_test
+    call per graph. Algorithmic bytes per launch: LexBFS as in the chordality
+    path (every pivot row once, order/rank/parent written); renaming of one
+    sweep: CSR read and written, bitset written, 11 int32 arrays of n; check:
+    order, row_ptr, col_idx and one rank per CSR entry."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_1508_06329_amd as lx
+
+    dev = torch.device("cuda:0")
+    t = time.time()
+    graphs = [gg.intervals(16384, 16, 0), gg.intervals(16384, 16, 1, unit=False), gg.intervals(65536, 12, 2)]
+    log(f"generated interval graphs in {time.time() - t:.1f}s")
+    dgs = lx.pack_graphs(graphs, dev)
+    lib = lx._lib.load()
+    stream = torch.cuda.current_stream()
+    wss = [torch.empty(int(lib.unit_interval_workspace_bytes(d.n, d.nnz)), dtype=torch.uint8, device=dev) for d in dgs]
+    res = torch.zeros((len(dgs), 8), dtype=torch.int32, device=dev)
+    descs = [d.desc() for d in dgs]
+
+    def step():
+        for i, d in enumerate(descs):
+            rc = lib.unit_interval_test(ctypes.byref(d), res[i].data_ptr(), None, wss[i].data_ptr(), wss[i].numel(),
+                                        stream.cuda_stream)
+            lx._lib.check(rc, "unit_interval_test")
+
+    step()
+    torch.cuda.synchronize()
+    refs = [oracle.unit_interval_test(g) for g in graphs]
+    got = res.cpu().numpy()
+    for g, r, row in zip(graphs, refs, got):
+        assert bool(row[0]) == r.unit_interval and tuple(int(x) for x in row[1:4]) == r.witness, g.name
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    with lx.KernelTimer() as kt:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        timing = kt.collect()
+    value = len(graphs) * args.steps / elapsed
+    row = lambda g: 8 * ((g.n + 63) // 64)
+    nnz = lambda g: len(g.col_idx)
+    ab = {"lexbfs": 3 * sum(g.n * row(g) + 12 * g.n for g in graphs),
+          "setup": 2 * sum(2 * 4 * (g.n + 1 + nnz(g)) + g.n * row(g) + 4 * (g.n + 1 + nnz(g)) + 44 * g.n
+                           for g in graphs),
+          "sweep": sum(4 * g.n + 4 * (g.n + 1) + 8 * nnz(g) for g in graphs), "certificate": 0}
+    per_kind = {}
+    for kind, (count, ms) in timing.items():
+        if count:
+            per_launch = ab.get(kind, 0) * args.steps / count
+            per_kind[kind] = {"launches": count, "avg_ms": ms / count, "bytes_per_launch": per_launch,
+                              "gbs": per_launch / (ms / count / 1e3) / 1e9}
+    dom = max(per_kind, key=lambda k: timing[k][1])
+    d = per_kind[dom]
+    log(f"{value:.2f} tests/s; " + ", ".join(f"{k} {v['avg_ms']:.3f} ms x{v['launches']}" for k, v in per_kind.items()))
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < args.cpu_seconds or done == 0:
+            oracle.unit_interval_test(graphs[done % len(graphs)])
+            done += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": done / el, "unit": "tests/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} tests of the same graphs in order ({el:.1f}s, one thread: three LexBFS "
+                         f"partition-refinement sweeps with renaming, then the neighbourhood check)"}
+        log(f"cpu oracle: {cpu['value']:.2f} tests/s")
+    print(json.dumps({
+        "metric": "unit interval tests/s (three-sweep LexBFS+ test) on 1 MI355X",
+        "value": value, "unit": "tests/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "interval: N=16,384 unit intervals (avg degree 16), N=16,384 mixed lengths "
+                               "(avg degree 16), N=65,536 unit intervals (avg degree 12), seeds 0-2",
+                   "graphs": len(graphs), "parallelism": "1 GPU"},
+        "verdicts": [bool(r.unit_interval) for r in refs],
+        "roofline": {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "avg_launch_ms": d["avg_ms"],
+                     "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
+        "kernels": per_kind,
+        "cpu_baseline": cpu,
+    }), flush=True)
+
+
 def cpu_oracle_rate(graphs, seconds, threads, ordering="lexbfs"):
     """The oracle (unchanged) over the workload's graphs in generation order
     on `threads` host threads (ctypes releases the GIL), for about `seconds`
@@ -297,6 +394,8 @@ def main():
         return bench_copy(args)
     if args.workload == "ingest":
         return bench_ingest(args)
+    if args.workload == "interval":
+        return bench_interval(args)
     t = time.time()
     if args.workload == "batch":
         graphs = gg.config_batch()

@@ -257,6 +257,63 @@ int lexbfs_build_bitset(int32_t n, const int32_t *row_ptr, const int32_t *col_id
  * workgroups. Negative LEXBFS_E* code on a HIP failure. */
 int32_t lexbfs_batch_max_n(void);
 
+/*
+ * Multi-sweep LexBFS. Section 3.2 surveys LexBFS as the core of interval
+ * graph recognition and Section 8 leaves a parallel interval test as future
+ * work; these entry points are the first step of that direction.
+ *
+ * lexbfs_plus_order -- one LexBFS+ sweep: the LexBFS of Section 4.1 with
+ * ties between equal labels going to the vertex that comes LAST in
+ * prev_order (instead of the smallest id). Computed by renaming every vertex
+ * v to n-1-(position of v in prev_order) on the device -- the tie rule then
+ * picks the smallest new id -- building the renamed CSR and bitset in the
+ * workspace, running the LexBFS kernel of lexbfs_order, and renaming the
+ * result back.
+ *   g           CSR part only (g->bits is not read; it may be NULL)
+ *   prev_order  DEVICE [n], a permutation of 0..n-1
+ *   order       DEVICE [n], written (required)
+ *   rank,parent DEVICE [n] or NULL, as for lexbfs_order (parent = latest
+ *               earlier neighbour in this order)
+ *   ws          lexbfs_plus_workspace_bytes(n, nnz) bytes (about
+ *               n*ceil(n/64)*8 for the renamed bitset + 4*nnz + 52*n)
+ * If prev_order is not a permutation (detected on the device) order, rank
+ * and parent are filled with -1. Errors: as lexbfs_order.
+ */
+size_t lexbfs_plus_workspace_bytes(int32_t n, int64_t nnz);
+int lexbfs_plus_order(const lexbfs_graph_t *g, const int32_t *prev_order, int32_t *order, int32_t *rank,
+                      int32_t *parent, void *ws, size_t ws_bytes, void *stream);
+
+/* Verdict of unit_interval_test, written to device memory (32 bytes).
+ * unit_interval = 1: the third order puts every closed neighbourhood on
+ *   consecutive positions (a unit interval ordering); witness = -1.
+ * unit_interval = 0: witness = (a, b, c) with a before b before c in the
+ *   third order, ac an edge and b not adjacent to both a and c. With v the
+ *   earliest vertex whose closed neighbourhood N[v] is not consecutive,
+ *   [lo, hi] the positions N[v] spans and b the earliest vertex of the span
+ *   outside N[v]: (vertex at lo, b, v) if b comes before v, else
+ *   (v, b, vertex at hi). */
+typedef struct lexbfs_interval_result {
+    int32_t unit_interval;
+    int32_t witness[3];
+    int32_t reserved[4];
+} lexbfs_interval_result_t;
+
+/*
+ * unit_interval_test -- Corneil's three-sweep unit interval recognition
+ * (Discrete Applied Mathematics 138 (2004)): sigma1 = LexBFS (lexbfs_order's
+ * order), sigma2 = LexBFS+ after sigma1, sigma3 = LexBFS+ after sigma2; the
+ * graph is a unit interval graph iff every closed neighbourhood is
+ * consecutive in sigma3. All steps run on `stream`.
+ *   g      full graph (CSR and bitset)
+ *   res    DEVICE lexbfs_interval_result_t, written (required)
+ *   order  DEVICE [n] or NULL: sigma3
+ *   ws     unit_interval_workspace_bytes(n, nnz) bytes
+ * Errors: as chordal_test.
+ */
+size_t unit_interval_workspace_bytes(int32_t n, int64_t nnz);
+int unit_interval_test(const lexbfs_graph_t *g, lexbfs_interval_result_t *res, int32_t *order, void *ws,
+                       size_t ws_bytes, void *stream);
+
 /* Library ABI version (incremented on incompatible changes). */
 int lexbfs_abi_version(void);
 

@@ -4,7 +4,9 @@ Python binding of ``liblexbfs.so`` (C ABI in ``include/lexbfs.h``). PyTorch
 supplies device memory and streams; every step of the path runs in the HIP
 kernels: the LexBFS order (Section 6.1 of Lupinska, "A Parallel Algorithm to
 Test Chordality of Graphs"), the perfect-elimination test (Section 6.2), and
-a chordless-cycle certificate for non-chordal graphs.
+a chordless-cycle certificate for non-chordal graphs. Multi-sweep LexBFS
+(LexBFS+) and the three-sweep unit interval test build on the same LexBFS
+kernel (the interval direction of Sections 3.2 and 8).
 """
 from __future__ import annotations
 
@@ -15,10 +17,11 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_MCS, LEXBFS_FLAG_PER_STEP, LEXBFS_MAX_N, LexbfsError, lexbfs_graph_t, lexbfs_outputs_t,
-                   lexbfs_result_t, lexbfs_tuning_t)
+from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_MCS, LEXBFS_FLAG_PER_STEP, LEXBFS_MAX_N, LexbfsError,
+                   lexbfs_graph_t, lexbfs_outputs_t, lexbfs_result_t, lexbfs_tuning_t)
 
 __all__ = ["BatchPlan", "pack_graphs", "build_bitset", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
+           "lexbfs_plus", "unit_interval_test", "IntervalResult",
            "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK",
            "LEXBFS_FLAG_PER_STEP", "LEXBFS_FLAG_MCS"]
 
@@ -163,6 +166,59 @@ def lexbfs_order(g: DeviceGraph, stream=None, ws: Optional[torch.Tensor] = None)
                           _stream_handle(stream))
     _lib.check(rc, "lexbfs_order")
     return order[:n], rank[:n], parent[:n]
+
+
+def lexbfs_plus(g: DeviceGraph, prev_order: torch.Tensor, stream=None, ws: Optional[torch.Tensor] = None):
+    """One LexBFS+ sweep after `prev_order` (int32 device tensor of n
+    vertices): (order, rank, parent) int32 device tensors. Ties go to the
+    vertex that comes last in prev_order."""
+    lib = _lib.load()
+    n = g.n
+    dev = g.device
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rank = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    parent = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if n > 0 and (prev_order.dtype != torch.int32 or prev_order.numel() != n or not prev_order.is_contiguous()):
+        raise ValueError("prev_order must be a contiguous int32 tensor of n entries")
+    need = int(lib.lexbfs_plus_workspace_bytes(n, g.nnz))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    d = g.desc()
+    rc = lib.lexbfs_plus_order(ctypes.byref(d), _ptr(prev_order) if n > 0 else None, _ptr(order), _ptr(rank),
+                               _ptr(parent), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _lib.check(rc, "lexbfs_plus_order")
+    return order[:n], rank[:n], parent[:n]
+
+
+@dataclass
+class IntervalResult:
+    unit_interval: Optional[bool]
+    witness: tuple                       # (a, b, c) or (-1, -1, -1)
+    order: Optional[torch.Tensor]        # the third sweep (device)
+    res_raw: Optional[torch.Tensor] = None
+
+
+def unit_interval_test(g: DeviceGraph, stream=None, ws: Optional[torch.Tensor] = None,
+                       sync: bool = True) -> IntervalResult:
+    """Three-sweep unit interval test (LexBFS, LexBFS+, LexBFS+, then every
+    closed neighbourhood consecutive in the third order). With sync=False
+    only res_raw and order are filled; read them after the stream."""
+    lib = _lib.load()
+    n = g.n
+    dev = g.device
+    res = torch.empty(8, dtype=torch.int32, device=dev)
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    need = int(lib.unit_interval_workspace_bytes(n, g.nnz))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    d = g.desc()
+    rc = lib.unit_interval_test(ctypes.byref(d), res.data_ptr(), _ptr(order), ws.data_ptr(), ws.numel(),
+                                _stream_handle(stream))
+    _lib.check(rc, "unit_interval_test")
+    if not sync:
+        return IntervalResult(None, (-1, -1, -1), order[:n], res)
+    r = res.tolist()
+    return IntervalResult(bool(r[0]), (r[1], r[2], r[3]), order[:n], res)
 
 
 def _result_from(row: torch.Tensor) -> tuple:

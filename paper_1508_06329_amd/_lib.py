@@ -32,7 +32,8 @@ KERNEL_KIND_NAMES = ("lexbfs", "sweep", "certificate", "setup")
 EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_order", "chordal_test", "lexbfs_batch_workspace_bytes",
             "chordal_test_batch", "lexbfs_batch_plan_create", "lexbfs_batch_plan_launch",
             "lexbfs_batch_plan_destroy", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_profile_enable",
-            "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_build_bitset", "lexbfs_abi_version"]
+            "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_build_bitset", "lexbfs_plus_workspace_bytes",
+            "lexbfs_plus_order", "unit_interval_workspace_bytes", "unit_interval_test", "lexbfs_abi_version"]
 
 
 class lexbfs_graph_t(ctypes.Structure):
@@ -50,6 +51,10 @@ class lexbfs_result_t(ctypes.Structure):
 class lexbfs_outputs_t(ctypes.Structure):
     _fields_ = [("order", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("parent", ctypes.c_void_p),
                 ("cycle", ctypes.c_void_p)]
+
+
+class lexbfs_interval_result_t(ctypes.Structure):
+    _fields_ = [("unit_interval", ctypes.c_int32), ("witness", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32 * 4)]
 
 
 class lexbfs_tuning_t(ctypes.Structure):
@@ -113,6 +118,14 @@ def load() -> ctypes.CDLL:
     lib.lexbfs_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.lexbfs_build_bitset.restype = ctypes.c_int
     lib.lexbfs_build_bitset.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp]
+    lib.lexbfs_plus_workspace_bytes.restype = sz
+    lib.lexbfs_plus_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    lib.lexbfs_plus_order.restype = ctypes.c_int
+    lib.lexbfs_plus_order.argtypes = [gp, vp, vp, vp, vp, vp, sz, vp]
+    lib.unit_interval_workspace_bytes.restype = sz
+    lib.unit_interval_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    lib.unit_interval_test.restype = ctypes.c_int
+    lib.unit_interval_test.argtypes = [gp, vp, vp, vp, sz, vp]
     lib.lexbfs_batch_max_n.restype = ctypes.c_int32
     lib.lexbfs_batch_max_n.argtypes = []
     lib.lexbfs_abi_version.restype = ctypes.c_int

@@ -688,6 +688,241 @@ __global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__re
 }
 
 // ---------------------------------------------------------------------------
+// Multi-sweep LexBFS and the unit interval test. Section 3.2 surveys LexBFS
+// as a building block of interval recognition and Section 8 leaves parallel
+// interval testing open; the three-sweep test here is Corneil's
+// (LexBFS, then LexBFS+ twice, then a check that every closed neighbourhood
+// is consecutive in the last order; Corneil, Discrete Applied Mathematics
+// 138 (2004)).
+//
+// A LexBFS+ sweep breaks ties between equal labels in favour of the vertex
+// that comes last in a previous order prev. Renaming v to n-1-pos(v), with
+// pos(v) the position of v in prev, makes that vertex the one of smallest
+// new id, so a sweep is: rename the graph on the device (CSR, then bitset),
+// run the LexBFS kernel unchanged, and rename its order back. New id a is
+// old vertex prev[n-1-a], so only neighbour ids need pos. Renamed rows keep
+// the order of their original entries (they are not ascending): the LexBFS
+// kernel reads a CSR row only for its length and the parent pass only for a
+// maximum over it, and neither depends on the order of the entries.
+// ---------------------------------------------------------------------------
+constexpr int kPlusThreads = 256;
+constexpr int kPlusScanThreads = 1024;
+constexpr int kPlusPerLane = LEXBFS_MAX_N / kPlusScanThreads;  // rows summed by one lane of the scan
+
+// pos[v] = -1 for every v, flag = 0, and (when given) the interval key to
+// "no failure".
+__global__ __launch_bounds__(kPlusThreads) void k_plus_init(int n, int32_t *pos, int32_t *flag, uint32_t *key)
+{
+    const int i = blockIdx.x * kPlusThreads + threadIdx.x;
+    if (i < n) pos[i] = -1;
+    if (i == 0) {
+        *flag = 0;
+        if (key) *key = kNoFail;
+    }
+}
+
+// pos[prev[i]] = i. flag becomes 1 unless prev is a permutation of 0..n-1
+// (an id out of range, or an id seen twice).
+__global__ __launch_bounds__(kPlusThreads) void k_plus_inverse(int n, const int32_t *__restrict__ prev,
+                                                               int32_t *pos, int32_t *flag)
+{
+    const int i = blockIdx.x * kPlusThreads + threadIdx.x;
+    if (i >= n) return;
+    const int v = prev[i];
+    if ((unsigned)v >= (unsigned)n || atomicExch(&pos[v], i) != -1) atomicOr(flag, 1);
+}
+
+// deg[a] = degree of old vertex prev[n-1-a] for a < n, 0 up to npad (a
+// multiple of kPlusPerLane); all 0 when prev is not a permutation, which
+// turns the renamed graph into an edgeless one.
+__global__ __launch_bounds__(kPlusThreads) void k_plus_degree(int n, int npad, const int32_t *__restrict__ prev,
+                                                              const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ flag, int32_t *deg)
+{
+    const int a = blockIdx.x * kPlusThreads + threadIdx.x;
+    if (a >= npad) return;
+    int d = 0;
+    if (a < n && *flag == 0) {
+        const int v = prev[n - 1 - a];
+        d = rp[v + 1] - rp[v];
+    }
+    deg[a] = d;
+}
+
+// rp2 = exclusive prefix sum of deg (n+1 entries). One workgroup: lane t
+// loads its kPlusPerLane consecutive degrees with 16-byte loads, the team
+// scans the lane totals, and each lane writes its run of row pointers.
+__global__ __launch_bounds__(kPlusScanThreads) void k_plus_scan(int n, const int32_t *__restrict__ deg_,
+                                                                int32_t *rp2)
+{
+    __shared__ uint32_t red[kPlusScanThreads / kWave];
+    const int t = threadIdx.x;
+    const int a0 = t * kPlusPerLane;
+    const int4 *deg = (const int4 *)deg_;
+    int4 x[kPlusPerLane / 4];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPlusPerLane / 4; ++k) {
+        x[k] = a0 < n ? deg[a0 / 4 + k] : make_int4(0, 0, 0, 0);
+        s += (uint32_t)(x[k].x + x[k].y + x[k].z + x[k].w);
+    }
+    BlockTeam<kPlusScanThreads, false> tm{t};
+    uint32_t off = tm.exclusive_scan(s, red);
+    if (t == 0) rp2[0] = 0;
+    if (a0 >= n) return;
+#pragma unroll
+    for (int k = 0; k < kPlusPerLane / 4; ++k) {
+        const int a = a0 + 4 * k;
+        const int d[4] = {x[k].x, x[k].y, x[k].z, x[k].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            off += (uint32_t)d[q];
+            if (a + q < n) rp2[a + q + 1] = (int32_t)off;
+        }
+    }
+}
+
+// Renamed CSR rows: one wavefront per new row a copies the row of old
+// vertex prev[n-1-a], each neighbour u renamed to n-1-pos[u]. Entries past
+// nnz (a row_ptr that disagrees with nnz) are dropped.
+__global__ __launch_bounds__(kPlusThreads) void k_plus_rows(int n, int64_t nnz, const int32_t *__restrict__ prev,
+                                                            const int32_t *__restrict__ pos,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const int32_t *__restrict__ flag,
+                                                            const int32_t *__restrict__ rp2, int32_t *ci2)
+{
+    if (*flag != 0) return;
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * (kPlusThreads / kWave);
+    for (int a = blockIdx.x * (kPlusThreads / kWave) + (threadIdx.x >> 6); a < n; a += stride) {
+        const int v = prev[n - 1 - a];
+        const int b = rp[v], e = rp[v + 1], o = rp2[a];
+        for (int j = b + lane; j < e; j += kWave) {
+            const int u = ci[j];
+            const int64_t q = (int64_t)o + (j - b);
+            if (q < nnz) ci2[q] = (unsigned)u < (unsigned)n ? n - 1 - pos[u] : u;
+        }
+    }
+}
+
+// The renamed sweep's outputs in old ids: order[i] = prev[n-1-order2[i]],
+// rank its inverse, parent[v] = the old id of the renamed parent. All -1
+// when prev is not a permutation.
+__global__ __launch_bounds__(kPlusThreads) void k_plus_map(int n, const int32_t *__restrict__ prev,
+                                                           const int32_t *__restrict__ order2,
+                                                           const int32_t *__restrict__ parent2,
+                                                           const int32_t *__restrict__ flag, int32_t *order,
+                                                           int32_t *rank, int32_t *parent)
+{
+    const int i = blockIdx.x * kPlusThreads + threadIdx.x;
+    if (i >= n) return;
+    const int a = order2[i];
+    if (*flag != 0 || (unsigned)a >= (unsigned)n) {
+        order[i] = -1;
+        if (rank) rank[i] = -1;
+        if (parent) parent[i] = -1;
+        return;
+    }
+    const int v = prev[n - 1 - a];
+    order[i] = v;
+    if (rank) rank[v] = i;
+    if (parent) {
+        const int p = parent2[a];
+        parent[v] = (unsigned)p < (unsigned)n ? prev[n - 1 - p] : -1;
+    }
+}
+
+// Unit interval check of an order: the closed neighbourhood of every vertex
+// must occupy consecutive positions. With rows free of repeats and
+// self-loops, N[v] of the vertex at position i is consecutive iff the span of
+// its positions (i included) is deg(v). One wavefront per position; key =
+// smallest failing position.
+__global__ __launch_bounds__(kPlusThreads) void k_ui_check(int n, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const int32_t *__restrict__ order,
+                                                           const int32_t *__restrict__ rank, uint32_t *key)
+{
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * (kPlusThreads / kWave);
+    for (int i = blockIdx.x * (kPlusThreads / kWave) + (threadIdx.x >> 6); i < n; i += stride) {
+        const int v = order[i];
+        const int b = rp[v], e = rp[v + 1];
+        uint32_t lo = (uint32_t)i, hi = (uint32_t)i;
+        for (int j = b + lane; j < e; j += kWave) {
+            const int u = ci[j];
+            const uint32_t r = (unsigned)u < (unsigned)n ? (uint32_t)rank[u] : (uint32_t)n;
+            lo = min(lo, r);
+            hi = max(hi, r);  // an id out of range counts as position n
+        }
+        lo = wave_min_u32(lo);
+        hi = wave_max_u32(hi);
+        if (lane == 0 && hi - lo != (uint32_t)(e - b)) atomicMin(key, (uint32_t)i);
+    }
+}
+
+// Verdict and witness. For the failing vertex v of smallest position i, with
+// [lo, hi] the span of N[v]: b is the earliest vertex in the span that is not
+// in N[v], and the triple is (order[lo], b, v) when b comes before v, else
+// (v, b, order[hi]): its first and last vertices are adjacent, the middle one
+// is not adjacent to both.
+__global__ __launch_bounds__(kFinishThreads) void k_ui_witness(int n, const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               const uint64_t *__restrict__ bits, int64_t W,
+                                                               const int32_t *__restrict__ order,
+                                                               const int32_t *__restrict__ rank,
+                                                               const uint32_t *__restrict__ key,
+                                                               lexbfs_interval_result_t *res)
+{
+    __shared__ uint32_t red[kFinishThreads / kWave];
+    const int t = threadIdx.x;
+    const uint32_t i = *key;
+    if (i == kNoFail) {
+        if (t == 0) {
+            res->unit_interval = 1;
+            res->witness[0] = res->witness[1] = res->witness[2] = -1;
+            for (int k = 0; k < 4; ++k) res->reserved[k] = 0;
+        }
+        return;
+    }
+    BlockTeam<kFinishThreads, false> tm{t};
+    const int v = order[i];
+    const int b = rp[v], e = rp[v + 1];
+    uint32_t lo = i, hi = i;
+    for (int j = b + t; j < e; j += kFinishThreads) {
+        const int u = ci[j];
+        const uint32_t r = (unsigned)u < (unsigned)n ? (uint32_t)rank[u] : (uint32_t)n;
+        lo = min(lo, r);
+        hi = max(hi, r);
+    }
+    lo = tm.min_all(lo, red);
+    hi = min(~tm.min_all(~hi, red), (uint32_t)n - 1);  // positions stay inside the order
+    const uint64_t *row = bits + (int64_t)v * W;
+    uint32_t cand = kNoFail;  // the first position of this lane's stride that is outside N[v]
+    for (uint32_t p = lo + t; p <= hi; p += kFinishThreads)
+        if (p != i && !test_bit(row, order[p])) {
+            cand = p;
+            break;
+        }
+    const uint32_t bp = tm.min_all(cand, red);
+    if (t == 0) {
+        res->unit_interval = 0;
+        if (bp == kNoFail) {  // cannot happen for a graph that meets the input contract
+            res->witness[0] = res->witness[1] = res->witness[2] = -1;
+        } else if (bp < i) {
+            res->witness[0] = order[lo];
+            res->witness[1] = order[bp];
+            res->witness[2] = v;
+        } else {
+            res->witness[0] = v;
+            res->witness[1] = order[bp];
+            res->witness[2] = order[hi];
+        }
+        for (int k = 0; k < 4; ++k) res->reserved[k] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -969,6 +1204,126 @@ BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
     L.arrays = off; off += arrays;
     L.total = off;
     return L;
+}
+
+// Launch of the bitset builder over n rows of W words each.
+int launch_build_bitset(int n, const int32_t *rp, const int32_t *ci, uint64_t *bits, int64_t W, hipStream_t s)
+{
+    const size_t lds = (size_t)(kBuildThreads / kWave) * 8 * (size_t)W;
+    const size_t lim = dynamic_lds_limit(k_build_bitset);
+    if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the bitset builder's LDS limit failed");
+    if (lds > lim) return fail_code(LEXBFS_ETOOBIG, "bitset row buffers do not fit the workgroup LDS");
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int per_block = kBuildThreads / kWave;
+    const int blocks = std::max(1, std::min((n + per_block - 1) / per_block, cus * 8));
+    hipLaunchKernelGGL(k_build_bitset, dim3(blocks), dim3(kBuildThreads), lds, s, n, rp, ci, bits, W);
+    LX_CHECK_LAUNCH("bitset builder launch");
+    return LEXBFS_OK;
+}
+
+// Workspace of one LexBFS+ sweep: validity flag, pos, padded degrees, the
+// renamed CSR and bitset, then a single-graph LexBFS workspace (which also
+// holds the renamed order and parents).
+struct PlusWs {
+    size_t flag, pos, deg, rp2, ci2, bits2, lex, total;
+};
+
+int plus_pad(int n) { return (std::max(n, 1) + kPlusPerLane - 1) / kPlusPerLane * kPlusPerLane; }
+
+PlusWs plus_layout(int n, int64_t nnz)
+{
+    PlusWs P;
+    const size_t m = (size_t)std::max(n, 1);
+    const size_t wn = (m + 63) / 64;
+    size_t off = 0;
+    P.flag = off; off += kAlign;
+    P.pos = off; off += al(m * 4);
+    P.deg = off; off += al((size_t)plus_pad(n) * 4);
+    P.rp2 = off; off += al((m + 1) * 4);
+    P.ci2 = off; off += al((size_t)std::max<int64_t>(nnz, 1) * 4);
+    P.bits2 = off; off += al(m * wn * 8);
+    P.lex = off; off += single_layout(n).total;
+    P.total = off;
+    return P;
+}
+
+// Workspace of the unit interval test: the first two orders, the third
+// order (when the caller keeps none) and its ranks, the failure key, then
+// a LexBFS+ sweep workspace (its LexBFS part also serves the first sweep).
+struct UiWs {
+    size_t key, s1, s2, s3, rank3, plus, total;
+};
+
+UiWs ui_layout(int n, int64_t nnz)
+{
+    UiWs U;
+    const size_t a = al((size_t)std::max(n, 1) * 4);
+    size_t off = 0;
+    U.key = off; off += kAlign;
+    U.s1 = off; off += a;
+    U.s2 = off; off += a;
+    U.s3 = off; off += a;
+    U.rank3 = off; off += a;
+    U.plus = off; off += plus_layout(n, nnz).total;
+    U.total = off;
+    return U;
+}
+
+// One LexBFS+ sweep of g after the order prev (all device pointers; rank
+// and parent may be null). The interval key, when given, is reset with the
+// sweep's other state.
+int plus_sweep(const lexbfs_graph_t *g, const int32_t *prev, int32_t *order, int32_t *rank, int32_t *parent,
+               char *ws, uint32_t *key, hipStream_t s)
+{
+    const int n = g->n;
+    const PlusWs P = plus_layout(n, g->nnz);
+    int32_t *flag = (int32_t *)(ws + P.flag);
+    int32_t *pos = (int32_t *)(ws + P.pos);
+    int32_t *deg = (int32_t *)(ws + P.deg);
+    int32_t *rp2 = (int32_t *)(ws + P.rp2);
+    int32_t *ci2 = (int32_t *)(ws + P.ci2);
+    uint64_t *bits2 = (uint64_t *)(ws + P.bits2);
+    const int blocks = (n + kPlusThreads - 1) / kPlusThreads;
+    const int npad = plus_pad(n);
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    {
+        ProfScope ps(3, s);
+        hipLaunchKernelGGL(k_plus_init, dim3(blocks), dim3(kPlusThreads), 0, s, n, pos, flag, key);
+        hipLaunchKernelGGL(k_plus_inverse, dim3(blocks), dim3(kPlusThreads), 0, s, n, prev, pos, flag);
+        hipLaunchKernelGGL(k_plus_degree, dim3((npad + kPlusThreads - 1) / kPlusThreads), dim3(kPlusThreads), 0, s,
+                           n, npad, prev, g->row_ptr, (const int32_t *)flag, deg);
+        hipLaunchKernelGGL(k_plus_scan, dim3(1), dim3(kPlusScanThreads), 0, s, n, (const int32_t *)deg, rp2);
+        const int rblocks = std::max(1, std::min((n + 3) / 4, cus * 8));
+        hipLaunchKernelGGL(k_plus_rows, dim3(rblocks), dim3(kPlusThreads), 0, s, n, g->nnz, prev, (const int32_t *)pos,
+                           g->row_ptr, g->col_idx, (const int32_t *)flag, (const int32_t *)rp2, ci2);
+        LX_CHECK_LAUNCH("LexBFS+ renaming launches");
+        const int rc = launch_build_bitset(n, rp2, ci2, bits2, (n + 63) / 64, s);
+        if (rc) return rc;
+    }
+    lexbfs_graph_t g2;
+    g2.n = n;
+    g2.reserved = 0;
+    g2.nnz = g->nnz;
+    g2.row_ptr = rp2;
+    g2.col_idx = ci2;
+    g2.bits = bits2;
+    g2.words_per_row = (n + 63) / 64;
+    const GDesc d = make_desc(&g2, ws + P.lex, single_layout(n), nullptr, nullptr, nullptr, nullptr, nullptr);
+    int rc = launch_lexbfs_single(d, s);
+    if (rc) return rc;
+    {
+        ProfScope ps(3, s);
+        hipLaunchKernelGGL(k_plus_map, dim3(blocks), dim3(kPlusThreads), 0, s, n, prev, (const int32_t *)d.order,
+                           (const int32_t *)d.parent, (const int32_t *)flag, order, rank, parent);
+    }
+    LX_CHECK_LAUNCH("LexBFS+ order launch");
+    return LEXBFS_OK;
 }
 
 }  // namespace
@@ -1332,19 +1687,78 @@ int lexbfs_build_bitset(int32_t n, const int32_t *row_ptr, const int32_t *col_id
     if (n == 0) return LEXBFS_OK;
     if (!row_ptr || !bits || words_per_row < (n + 63) / 64 || words_per_row > (int64_t)(LEXBFS_MAX_N / 64))
         return LEXBFS_EINVAL;
-    const size_t lds = (size_t)(kBuildThreads / kWave) * 8 * (size_t)words_per_row;
-    const size_t lim = dynamic_lds_limit(k_build_bitset);
-    if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the bitset builder's LDS limit failed");
-    if (lds > lim) return fail_code(LEXBFS_ETOOBIG, "bitset row buffers do not fit the workgroup LDS");
-    int cus = 256, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;
-    const int per_block = kBuildThreads / kWave;
-    const int blocks = std::max(1, std::min((n + per_block - 1) / per_block, cus * 8));
-    hipLaunchKernelGGL(k_build_bitset, dim3(blocks), dim3(kBuildThreads), lds, (hipStream_t)stream, n, row_ptr,
-                       col_idx, bits, words_per_row);
-    LX_CHECK_LAUNCH("bitset builder launch");
+    return launch_build_bitset(n, row_ptr, col_idx, bits, words_per_row, (hipStream_t)stream);
+}
+
+size_t lexbfs_plus_workspace_bytes(int32_t n, int64_t nnz)
+{
+    return plus_layout(std::max(n, 0), std::max<int64_t>(nnz, 0)).total;
+}
+
+int lexbfs_plus_order(const lexbfs_graph_t *g, const int32_t *prev_order, int32_t *order, int32_t *rank,
+                      int32_t *parent, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!g) return LEXBFS_EINVAL;
+    if (g->n < 0 || g->nnz < 0 || g->nnz >= (int64_t)1 << 31 || g->reserved != 0) return LEXBFS_EINVAL;
+    if (g->n > LEXBFS_MAX_N) return LEXBFS_ETOOBIG;
+    if (g->n == 0) return LEXBFS_OK;
+    if (!g->row_ptr || (g->nnz > 0 && !g->col_idx) || !prev_order || !order) return LEXBFS_EINVAL;
+    if (!ws || ws_bytes < plus_layout(g->n, g->nnz).total) return LEXBFS_ENOWS;
+    return plus_sweep(g, prev_order, order, rank, parent, (char *)ws, nullptr, (hipStream_t)stream);
+}
+
+size_t unit_interval_workspace_bytes(int32_t n, int64_t nnz)
+{
+    return ui_layout(std::max(n, 0), std::max<int64_t>(nnz, 0)).total;
+}
+
+int unit_interval_test(const lexbfs_graph_t *g, lexbfs_interval_result_t *res, int32_t *order, void *ws,
+                       size_t ws_bytes, void *stream)
+{
+    int rc = validate_graph(g);
+    if (rc) return rc;
+    if (!res) return LEXBFS_EINVAL;
+    const int n = g->n;
+    const UiWs U = ui_layout(n, g->nnz);
+    if (!ws || ws_bytes < U.total) return LEXBFS_ENOWS;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    uint32_t *key = (uint32_t *)(w + U.key);
+    int32_t *s1 = (int32_t *)(w + U.s1), *s2 = (int32_t *)(w + U.s2);
+    int32_t *s3 = order ? order : (int32_t *)(w + U.s3);
+    int32_t *rank3 = (int32_t *)(w + U.rank3);
+    char *pw = w + U.plus;
+    if (n == 0) {
+        ProfScope ps(3, s);
+        hipLaunchKernelGGL(k_plus_init, dim3(1), dim3(kPlusThreads), 0, s, 0, (int32_t *)nullptr,
+                           (int32_t *)(pw + plus_layout(0, 0).flag), key);
+        LX_CHECK_LAUNCH("interval key launch");
+    } else {
+        // Sweep 1: plain LexBFS, in the LexBFS part of the sweep workspace.
+        const PlusWs P = plus_layout(n, g->nnz);
+        const GDesc d1 = make_desc(g, pw + P.lex, single_layout(n), s1, nullptr, nullptr, nullptr, nullptr);
+        rc = launch_lexbfs_single(d1, s);
+        if (rc) return rc;
+        rc = plus_sweep(g, s1, s2, nullptr, nullptr, pw, nullptr, s);
+        if (rc) return rc;
+        rc = plus_sweep(g, s2, s3, rank3, nullptr, pw, key, s);
+        if (rc) return rc;
+        int cus = 256, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        ProfScope ps(1, s);
+        const int cblocks = std::max(1, std::min((n + 3) / 4, cus * 8));
+        hipLaunchKernelGGL(k_ui_check, dim3(cblocks), dim3(kPlusThreads), 0, s, n, g->row_ptr, g->col_idx,
+                           (const int32_t *)s3, (const int32_t *)rank3, key);
+        LX_CHECK_LAUNCH("interval check launch");
+    }
+    {
+        ProfScope ps(2, s);
+        hipLaunchKernelGGL(k_ui_witness, dim3(1), dim3(kFinishThreads), 0, s, n, g->row_ptr, g->col_idx, g->bits,
+                           g->words_per_row, (const int32_t *)s3, (const int32_t *)rank3, (const uint32_t *)key, res);
+    }
+    LX_CHECK_LAUNCH("interval witness launch");
     return LEXBFS_OK;
 }
 

@@ -1,0 +1,123 @@
+"""GPU parity of multi-sweep LexBFS (LexBFS+, lexbfs_plus_order) and of the
+three-sweep unit interval test (unit_interval_test) against the oracle,
+element by element: every sweep's order, rank and parent, the verdict, the
+third order and the witness triple."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1508_06329_amd as lx  # noqa: E402
+from test_gpu_parity import structured_cases  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def check_plus(g, prev, tag=""):
+    say(f"[plus] {tag} {g.name} n={g.n} m={g.m}")
+    ref = oracle.lexbfs_plus(g, prev)
+    d = lx.DeviceGraph.from_host(g, DEV)
+    order, rank, parent = lx.lexbfs_plus(d, torch.from_numpy(np.ascontiguousarray(prev, dtype=np.int32)).to(DEV))
+    assert np.array_equal(order.cpu().numpy(), ref.order), f"order {g.name}"
+    assert np.array_equal(rank.cpu().numpy(), ref.rank), f"rank {g.name}"
+    assert np.array_equal(parent.cpu().numpy(), ref.parent), f"parent {g.name}"
+
+
+def check_interval(g, tag=""):
+    say(f"[interval] {tag} {g.name} n={g.n} m={g.m}")
+    ref = oracle.unit_interval_test(g)
+    r = lx.unit_interval_test(lx.DeviceGraph.from_host(g, DEV))
+    assert r.unit_interval == ref.unit_interval, f"verdict {g.name}"
+    assert np.array_equal(r.order.cpu().numpy(), ref.order), f"third order {g.name}"
+    assert r.witness == ref.witness, f"witness {g.name}: {r.witness} vs {ref.witness}"
+    assert r.res_raw[4:].tolist() == [0, 0, 0, 0]
+    return r
+
+
+@pytest.mark.parametrize("idx", range(len(structured_cases())))
+def test_structured(idx):
+    g = structured_cases()[idx]
+    rng = np.random.default_rng(idx)
+    check_plus(g, rng.permutation(g.n).astype(np.int32), tag="structured")
+    check_plus(g, np.arange(g.n, dtype=np.int32), tag="structured identity")
+    check_interval(g, tag="structured")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_plus(seed):
+    rng = np.random.default_rng(100 + seed)
+    for g in (gg.gnp(700, 0.02, 10 + seed), gg.gnp(4097, 0.003, 20 + seed), gg.subtree(3000, 700, 10, 30 + seed),
+              gg.intervals(2000, 8, 40 + seed), gg.intervals(9000, 16, 50 + seed, unit=False)):
+        check_plus(g, rng.permutation(g.n).astype(np.int32), tag="random prev")
+        check_plus(g, oracle.lexbfs(g).order, tag="after LexBFS")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_generated_intervals(seed):
+    for n, deg in ((64, 6), (500, 10), (3000, 12), (12000, 20)):
+        r = check_interval(gg.intervals(n, deg, 200 + seed), tag="unit")
+        assert r.unit_interval
+        check_interval(gg.intervals(n, deg, 300 + seed, unit=False), tag="mixed lengths")
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_other_families(seed):
+    check_interval(gg.gnp(1500, 0.004, 70 + seed), tag="gnp")
+    check_interval(gg.subtree(2000, 500, 8, 80 + seed), tag="subtree")
+    for g in gg.split_pair(40, 400, 6, 90 + seed):
+        check_interval(g, tag="split")
+
+
+def test_full_size():
+    """n = 65,536 (the largest supported size): the global-table LexBFS form
+    in all three sweeps."""
+    check_interval(gg.intervals(65536, 12, 3), tag="N=65536 unit")
+    check_interval(gg.intervals(65536, 12, 4, unit=False), tag="N=65536 mixed")
+    g = gg.gnp(65536, 0.0002, 5)
+    check_plus(g, gg.permutation(g.n, 6), tag="N=65536 gnp")
+
+
+def test_prev_not_a_permutation():
+    """The device detects a prev_order that is not a permutation and fills
+    the outputs with -1."""
+    g = gg.gnp(300, 0.05, 9)
+    d = lx.DeviceGraph.from_host(g, DEV)
+    for prev in (np.zeros(g.n, dtype=np.int32), np.arange(g.n, dtype=np.int32) + 1):
+        say(f"[plus] invalid prev {prev[:3].tolist()}")
+        order, rank, parent = lx.lexbfs_plus(d, torch.from_numpy(prev).to(DEV))
+        for t in (order, rank, parent):
+            assert (t.cpu().numpy() == -1).all()
+    check_plus(g, gg.permutation(g.n, 4), tag="valid prev after invalid ones")
+
+
+def test_workspace_and_stream_reuse():
+    """Back-to-back calls on one workspace on a side stream give the
+    oracle's results each time."""
+    graphs = [gg.intervals(1000, 8, 11), gg.intervals(5000, 10, 12, unit=False), gg.gnp(800, 0.01, 13)]
+    lib = lx._lib.load()
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    need = max(int(lib.unit_interval_workspace_bytes(d.n, d.nnz)) for d in dgs)
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    rs = [lx.unit_interval_test(d, stream=s, ws=ws, sync=False) for d in dgs]
+    s.synchronize()
+    for g, r in zip(graphs, rs):
+        ref = oracle.unit_interval_test(g)
+        raw = r.res_raw.tolist()
+        assert bool(raw[0]) == ref.unit_interval and tuple(raw[1:4]) == ref.witness, g.name
+        assert np.array_equal(r.order.cpu().numpy(), ref.order), g.name
