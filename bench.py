@@ -15,7 +15,7 @@ on an evenly spaced sample of the same graphs, and the CPU oracle on a
 bounded sample on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                      [--workload batch|single-small|single-large|split|serving|copy|ingest|interval]
+                      [--workload batch|single-small|single-large|split|serving|copy|ingest|interval|interval-batch]
 """
 import argparse
 import json
@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "single-small", "single-large", "split", "serving", "copy", "ingest", "interval"])
+                    choices=["batch", "single-small", "single-large", "split", "serving", "copy", "ingest", "interval",
+                             "interval-batch"])
     ap.add_argument("--serving-pool", type=int, default=192)
     ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--per-graph-sample", type=int, default=512)
@@ -243,13 +244,21 @@ def bench_ingest(args):
 
 def bench_interval(args):
     """Three-sweep unit interval test (LexBFS, LexBFS+, LexBFS+, then the
-    consecutive-neighbourhood check) on N = 16,384 interval graphs of unit
-    and of mixed lengths and an N = 65,536 unit interval graph (average
-    degree 16, 16 and 12; ids shuffled). A step is one unit_interval_test
-    call per graph. Algorithmic bytes per launch: LexBFS as in the chordality
-    path (every pivot row once, order/rank/parent written); renaming of one
-    sweep: CSR read and written, bitset written, 11 int32 arrays of n; check:
-    order, row_ptr, col_idx and one rank per CSR entry."""
+    consecutive-neighbourhood check).
+
+    interval: N = 16,384 interval graphs of unit and of mixed lengths and an
+    N = 65,536 unit interval graph (average degree 16, 16 and 12); a step is
+    one unit_interval_test call per graph.
+    interval-batch: 4,096 graphs with the batch workload's size and kind
+    draws (N log-uniform on [32, 4096]; 50% unit intervals, 25% G(n, p),
+    25% mixed lengths; average degree 8); a step is one
+    unit_interval_test_batch call, host preparation included; the per-graph
+    path is timed on a sample.
+
+    Algorithmic bytes per launch: LexBFS as in the chordality path (every
+    pivot row once, order/rank/parent written); renaming of one sweep: CSR
+    read and written, bitset written, 11 int32 arrays of n; check: order,
+    row_ptr, col_idx and one rank per CSR entry."""
     import ctypes
 
     import numpy as np
@@ -260,28 +269,47 @@ def bench_interval(args):
     import paper_1508_06329_amd as lx
 
     dev = torch.device("cuda:0")
+    batched = args.workload == "interval-batch"
     t = time.time()
-    graphs = [gg.intervals(16384, 16, 0), gg.intervals(16384, 16, 1, unit=False), gg.intervals(65536, 12, 2)]
-    log(f"generated interval graphs in {time.time() - t:.1f}s")
+    if batched:
+        graphs = gg.config_interval_batch()
+        wl = ("interval-batch: 4,096 graphs, N log-uniform on [32, 4096], 50% unit intervals / 25% G(n,p) / 25% "
+              "intervals of mixed lengths, average degree 8, seed 0")
+    else:
+        graphs = [gg.intervals(16384, 16, 0), gg.intervals(16384, 16, 1, unit=False), gg.intervals(65536, 12, 2)]
+        wl = ("interval: N=16,384 unit intervals (avg degree 16), N=16,384 mixed lengths (avg degree 16), "
+              "N=65,536 unit intervals (avg degree 12), seeds 0-2")
+    log(f"generated {len(graphs)} interval-workload graphs in {time.time() - t:.1f}s")
     dgs = lx.pack_graphs(graphs, dev)
     lib = lx._lib.load()
     stream = torch.cuda.current_stream()
-    wss = [torch.empty(int(lib.unit_interval_workspace_bytes(d.n, d.nnz)), dtype=torch.uint8, device=dev) for d in dgs]
-    res = torch.zeros((len(dgs), 8), dtype=torch.int32, device=dev)
-    descs = [d.desc() for d in dgs]
+    count = len(dgs)
+    res = torch.zeros((count, 8), dtype=torch.int32, device=dev)
+    if batched:
+        descs = (lx.lexbfs_graph_t * count)(*[d.desc() for d in dgs])
+        ws = torch.empty(int(lib.unit_interval_batch_workspace_bytes(descs, count)), dtype=torch.uint8, device=dev)
 
-    def step():
-        for i, d in enumerate(descs):
-            rc = lib.unit_interval_test(ctypes.byref(d), res[i].data_ptr(), None, wss[i].data_ptr(), wss[i].numel(),
-                                        stream.cuda_stream)
-            lx._lib.check(rc, "unit_interval_test")
+        def step():
+            lx._lib.check(lib.unit_interval_test_batch(descs, count, res.data_ptr(), None, ws.data_ptr(), ws.numel(),
+                                                       stream.cuda_stream), "unit_interval_test_batch")
+    else:
+        wss = [torch.empty(int(lib.unit_interval_workspace_bytes(d.n, d.nnz)), dtype=torch.uint8, device=dev)
+               for d in dgs]
+        descs = [d.desc() for d in dgs]
+
+        def step():
+            for i, d in enumerate(descs):
+                rc = lib.unit_interval_test(ctypes.byref(d), res[i].data_ptr(), None, wss[i].data_ptr(),
+                                            wss[i].numel(), stream.cuda_stream)
+                lx._lib.check(rc, "unit_interval_test")
 
     step()
     torch.cuda.synchronize()
-    refs = [oracle.unit_interval_test(g) for g in graphs]
     got = res.cpu().numpy()
-    for g, r, row in zip(graphs, refs, got):
-        assert bool(row[0]) == r.unit_interval and tuple(int(x) for x in row[1:4]) == r.witness, g.name
+    chk = range(0, count, max(1, count // 256))  # verdicts checked against the oracle on a spread sample
+    refs = {i: oracle.unit_interval_test(graphs[i]) for i in chk}
+    for i, r in refs.items():
+        assert bool(got[i][0]) == r.unit_interval and tuple(int(x) for x in got[i][1:4]) == r.witness, graphs[i].name
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -292,7 +320,7 @@ def bench_interval(args):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         timing = kt.collect()
-    value = len(graphs) * args.steps / elapsed
+    value = count * args.steps / elapsed
     row = lambda g: 8 * ((g.n + 63) // 64)
     nnz = lambda g: len(g.col_idx)
     ab = {"lexbfs": 3 * sum(g.n * row(g) + 12 * g.n for g in graphs),
@@ -300,39 +328,61 @@ def bench_interval(args):
                            for g in graphs),
           "sweep": sum(4 * g.n + 4 * (g.n + 1) + 8 * nnz(g) for g in graphs), "certificate": 0}
     per_kind = {}
-    for kind, (count, ms) in timing.items():
-        if count:
-            per_launch = ab.get(kind, 0) * args.steps / count
-            per_kind[kind] = {"launches": count, "avg_ms": ms / count, "bytes_per_launch": per_launch,
-                              "gbs": per_launch / (ms / count / 1e3) / 1e9}
+    for kind, (cnt, ms) in timing.items():
+        if cnt:
+            per_launch = ab.get(kind, 0) * args.steps / cnt
+            per_kind[kind] = {"launches": cnt, "avg_ms": ms / cnt, "bytes_per_launch": per_launch,
+                              "gbs": per_launch / (ms / cnt / 1e3) / 1e9}
     dom = max(per_kind, key=lambda k: timing[k][1])
     d = per_kind[dom]
     log(f"{value:.2f} tests/s; " + ", ".join(f"{k} {v['avg_ms']:.3f} ms x{v['launches']}" for k, v in per_kind.items()))
+    per_graph = None
+    if batched and args.per_graph_sample > 0:
+        idx = np.linspace(0, count - 1, min(args.per_graph_sample, count)).astype(int)
+        maxd = max(idx, key=lambda i: int(lib.unit_interval_workspace_bytes(dgs[i].n, dgs[i].nnz)))
+        ws1 = torch.empty(int(lib.unit_interval_workspace_bytes(dgs[maxd].n, dgs[maxd].nnz)), dtype=torch.uint8,
+                          device=dev)
+        d1 = [dgs[i].desc() for i in idx]
+
+        def one(dd):
+            lx._lib.check(lib.unit_interval_test(ctypes.byref(dd), res[0].data_ptr(), None, ws1.data_ptr(),
+                                                 ws1.numel(), stream.cuda_stream), "unit_interval_test")
+
+        for dd in d1[:8]:
+            one(dd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for dd in d1:
+            one(dd)
+        torch.cuda.synchronize()
+        pg = len(d1) / (time.perf_counter() - t0)
+        per_graph = {"tests_per_s": pg, "sample_graphs": len(d1), "batched_speedup": value / pg}
+        log(f"per-graph path: {pg:.1f} tests/s")
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         done = 0
         while time.perf_counter() - t0 < args.cpu_seconds or done == 0:
-            oracle.unit_interval_test(graphs[done % len(graphs)])
+            oracle.unit_interval_test(graphs[done % count])
             done += 1
         el = time.perf_counter() - t0
         cpu = {"value": done / el, "unit": "tests/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} tests of the same graphs in order ({el:.1f}s, one thread: three LexBFS "
-                         f"partition-refinement sweeps with renaming, then the neighbourhood check)"}
+               "sample": f"{done} tests of the same graphs in generation order ({el:.1f}s, one thread: three "
+                         f"partition-refinement LexBFS sweeps with renaming, then the neighbourhood check)"}
         log(f"cpu oracle: {cpu['value']:.2f} tests/s")
     print(json.dumps({
         "metric": "unit interval tests/s (three-sweep LexBFS+ test) on 1 MI355X",
         "value": value, "unit": "tests/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "interval: N=16,384 unit intervals (avg degree 16), N=16,384 mixed lengths "
-                               "(avg degree 16), N=65,536 unit intervals (avg degree 12), seeds 0-2",
-                   "graphs": len(graphs), "parallelism": "1 GPU"},
-        "verdicts": [bool(r.unit_interval) for r in refs],
+        "config": {"workload": wl, "graphs": count, "sum_n": sum(g.n for g in graphs),
+                   "sum_m": sum(g.m for g in graphs), "parallelism": "1 GPU"},
+        "unit_interval_graphs": int(sum(int(x) for x in got[:, 0])),
         "roofline": {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "avg_launch_ms": d["avg_ms"],
                      "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
         "kernels": per_kind,
+        "per_graph": per_graph,
         "cpu_baseline": cpu,
     }), flush=True)
 
@@ -394,7 +444,7 @@ def main():
         return bench_copy(args)
     if args.workload == "ingest":
         return bench_ingest(args)
-    if args.workload == "interval":
+    if args.workload in ("interval", "interval-batch"):
         return bench_interval(args)
     t = time.time()
     if args.workload == "batch":

@@ -227,7 +227,7 @@ def relabel(g: Graph, perm: np.ndarray) -> Graph:
     dst = g.col_idx.astype(np.int64)
     keep = src < dst
     e = np.stack([perm[src[keep]], perm[dst[keep]]], axis=1)
-    return from_edges(g.n, [tuple(x) for x in e.tolist()], f"relabel({g.name})")
+    return from_edges(g.n, e, f"relabel({g.name})")
 
 
 def permutation(n: int, seed: int) -> np.ndarray:
@@ -249,14 +249,14 @@ def intervals(n: int, avg_deg: float, seed: int, unit: bool = True) -> Graph:
     left = u[:n] * span
     right = left + (1.0 if unit else 2.0 * u[n:])
     idx = np.argsort(left, kind="stable")
-    edges = []
-    for a in range(n):  # sweep by left end: b intersects a iff left[b] <= right[a]
-        i = idx[a]
-        for b in range(a + 1, n):
-            j = idx[b]
-            if left[j] > right[i]:
-                break
-            edges.append((int(i), int(j)))
+    # In left-end order, interval a meets the later intervals b with
+    # left[b] <= right[a]: positions a+1 .. hi[a]-1.
+    hi = np.searchsorted(left[idx], right[idx], side="right")
+    cnt = np.maximum(hi - np.arange(n) - 1, 0)
+    src = np.repeat(np.arange(n), cnt)
+    first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    dst = src + 1 + (np.arange(int(cnt.sum())) - first)
+    edges = np.stack([idx[src], idx[dst]], axis=1).astype(np.int32)
     g = from_edges(n, edges, f"{'unit_' if unit else ''}intervals({n},{avg_deg})")
     return relabel(g, permutation(n, seed + 1))
 
@@ -326,5 +326,27 @@ def config_batch(count: int = 4096, lo: int = 32, hi: int = 4096, seed: int = 0)
         return mix_graph(int(ns[i]), int(kinds[i]), int(Ls[i]), graph_seed(seed, 1000 + i))
 
     # the C generators release the GIL; results are independent of the pool
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(count)))
+
+
+def interval_mix_graph(n: int, kind: int, seed: int) -> Graph:
+    """One graph of the interval batch mix, average degree 8: kind 0 = unit
+    intervals, 1 = GNP(n, 8/(n-1)), 2 = intervals of mixed lengths."""
+    if kind == 1:
+        return gnp(n, min(1.0, 8.0 / max(1, n - 1)), seed)
+    return intervals(n, 8.0, seed, unit=kind == 0)
+
+
+def config_interval_batch(count: int = 4096, lo: int = 32, hi: int = 4096, seed: int = 0) -> List[Graph]:
+    """Interval batch: the sizes and kind draws of the batch mix (N
+    log-uniform on [lo, hi]); 50% unit interval graphs, 25% GNP with average
+    degree 8, 25% interval graphs of mixed lengths."""
+    ns, kinds, _, _ = mix_specs(count, lo, hi, seed)
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
+        return interval_mix_graph(int(ns[i]), int(kinds[i]), graph_seed(seed, 2000 + i))
+
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         return list(ex.map(one, range(count)))

@@ -314,6 +314,24 @@ size_t unit_interval_workspace_bytes(int32_t n, int64_t nnz);
 int unit_interval_test(const lexbfs_graph_t *g, lexbfs_interval_result_t *res, int32_t *order, void *ws,
                        size_t ws_bytes, void *stream);
 
+/*
+ * unit_interval_test_batch -- unit_interval_test on `count` graphs with one
+ * launch per step for the whole batch: the three sweeps are batch passes of
+ * the chordal_test_batch kernels (order only), and renaming, bitset build,
+ * mapping back and the check each cover every graph in one launch.
+ * Results are those of unit_interval_test on each graph.
+ *   gs      HOST array of `count` graphs (device pointers inside)
+ *   res     DEVICE array of `count` lexbfs_interval_result_t, written
+ *   orders  HOST array of `count` DEVICE pointers ([n_i] int32, sigma3 of
+ *           graph i) or NULL entries; or NULL
+ *   ws      unit_interval_batch_workspace_bytes(gs, count) bytes
+ * Host-side preparation (two batch plans) happens inside the call.
+ * Errors: as chordal_test_batch.
+ */
+size_t unit_interval_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count);
+int unit_interval_test_batch(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result_t *res,
+                             int32_t *const *orders, void *ws, size_t ws_bytes, void *stream);
+
 /* Library ABI version (incremented on incompatible changes). */
 int lexbfs_abi_version(void);
 

@@ -21,7 +21,7 @@ from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_MCS, LEXBFS_FLAG_PER_
                    lexbfs_graph_t, lexbfs_outputs_t, lexbfs_result_t, lexbfs_tuning_t)
 
 __all__ = ["BatchPlan", "pack_graphs", "build_bitset", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
-           "lexbfs_plus", "unit_interval_test", "IntervalResult",
+           "lexbfs_plus", "unit_interval_test", "unit_interval_test_batch", "IntervalResult",
            "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK",
            "LEXBFS_FLAG_PER_STEP", "LEXBFS_FLAG_MCS"]
 
@@ -219,6 +219,39 @@ def unit_interval_test(g: DeviceGraph, stream=None, ws: Optional[torch.Tensor] =
         return IntervalResult(None, (-1, -1, -1), order[:n], res)
     r = res.tolist()
     return IntervalResult(bool(r[0]), (r[1], r[2], r[3]), order[:n], res)
+
+
+def unit_interval_test_batch(graphs: Sequence[DeviceGraph], stream=None, outputs: bool = False,
+                             ws: Optional[torch.Tensor] = None, sync: bool = True) -> List[IntervalResult]:
+    """unit_interval_test on every graph, batched (one launch per step for
+    the whole batch). With outputs=True each result carries its third
+    order; with sync=False only res_raw (a row of the shared verdict tensor)
+    and order are filled."""
+    lib = _lib.load()
+    count = len(graphs)
+    if count == 0:
+        return []
+    dev = graphs[0].device
+    descs = (lexbfs_graph_t * count)(*[g.desc() for g in graphs])
+    res = torch.empty((count, 8), dtype=torch.int32, device=dev)
+    orders = [torch.empty(max(g.n, 1), dtype=torch.int32, device=dev) for g in graphs] if outputs else None
+    optr = (ctypes.c_void_p * count)(*[o.data_ptr() for o in orders]) if outputs else None
+    need = int(lib.unit_interval_batch_workspace_bytes(descs, count))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    rc = lib.unit_interval_test_batch(descs, count, res.data_ptr(), optr, ws.data_ptr(), ws.numel(),
+                                      _stream_handle(stream))
+    _lib.check(rc, "unit_interval_test_batch")
+    out = []
+    rows = res.tolist() if sync else None
+    for i, g in enumerate(graphs):
+        order = orders[i][:g.n] if outputs else None
+        if sync:
+            r = rows[i]
+            out.append(IntervalResult(bool(r[0]), (r[1], r[2], r[3]), order, res[i]))
+        else:
+            out.append(IntervalResult(None, (-1, -1, -1), order, res[i]))
+    return out
 
 
 def _result_from(row: torch.Tensor) -> tuple:

@@ -33,7 +33,8 @@ EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_order", "chordal_test", "lexbfs_ba
             "chordal_test_batch", "lexbfs_batch_plan_create", "lexbfs_batch_plan_launch",
             "lexbfs_batch_plan_destroy", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_profile_enable",
             "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_build_bitset", "lexbfs_plus_workspace_bytes",
-            "lexbfs_plus_order", "unit_interval_workspace_bytes", "unit_interval_test", "lexbfs_abi_version"]
+            "lexbfs_plus_order", "unit_interval_workspace_bytes", "unit_interval_test",
+            "unit_interval_batch_workspace_bytes", "unit_interval_test_batch", "lexbfs_abi_version"]
 
 
 class lexbfs_graph_t(ctypes.Structure):
@@ -126,6 +127,10 @@ def load() -> ctypes.CDLL:
     lib.unit_interval_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64]
     lib.unit_interval_test.restype = ctypes.c_int
     lib.unit_interval_test.argtypes = [gp, vp, vp, vp, sz, vp]
+    lib.unit_interval_batch_workspace_bytes.restype = sz
+    lib.unit_interval_batch_workspace_bytes.argtypes = [gp, ctypes.c_int32]
+    lib.unit_interval_test_batch.restype = ctypes.c_int
+    lib.unit_interval_test_batch.argtypes = [gp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_void_p), vp, sz, vp]
     lib.lexbfs_batch_max_n.restype = ctypes.c_int32
     lib.lexbfs_batch_max_n.argtypes = []
     lib.lexbfs_abi_version.restype = ctypes.c_int

@@ -27,6 +27,9 @@ constexpr size_t kAlign = 256;
 constexpr int kSweepThreads = 256;
 constexpr int kFinishThreads = 256;
 constexpr int kBatchThreads = 256;
+// Internal plan flag (never accepted from callers): LexBFS order, rank and
+// parent only, without the test's verdict, witness and certificate.
+constexpr uint32_t kFlagOrderOnly = 0x80000000u;
 
 // Description of the last failure on this thread (lexbfs_last_error).
 thread_local char t_last_error[256] = "";
@@ -564,7 +567,7 @@ __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32
                                                   B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
     }
     tm.sync_mem();  // order, rank, parent and the failing rank visible to the team
-    finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
+    if (!(flags & kFlagOrderOnly)) finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
     tm.sync();        // the region is reused by the team's next graph
 }
 
@@ -577,19 +580,17 @@ __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32
 // ---------------------------------------------------------------------------
 constexpr int kBuildThreads = 256;
 
-__global__ __launch_bounds__(kBuildThreads) void k_build_bitset(int n, const int32_t *__restrict__ rp_,
-                                                                const int32_t *__restrict__ ci_, uint64_t *bits_,
-                                                                int64_t W)
+// Rows first, first + stride, ... of one graph, one wavefront at a time;
+// `row` is this wavefront's LDS buffer of W words.
+__device__ __forceinline__ void build_rows(int n, const int32_t *rp_, const int32_t *ci_, uint64_t *bits_, int64_t W,
+                                           uint64_t *row, int first, int stride)
 {
-    extern __shared__ uint64_t lds[];
     LX_GLOBAL const int32_t *rp = as_global(rp_);
     LX_GLOBAL const int32_t *ci = as_global(ci_);
     LX_GLOBAL uint64_t *bits = as_global(bits_);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint64_t *row = lds + (int64_t)wave * W;
+    const int lane = threadIdx.x & 63;
     const int64_t lim = W << 6;  // ids beyond the row's words are ignored
-    const int stride = gridDim.x * (kBuildThreads / kWave);
-    for (int v = blockIdx.x * (kBuildThreads / kWave) + wave; v < n; v += stride) {
+    for (int v = first; v < n; v += stride) {
         for (int64_t w = lane; w < W; w += kWave) row[w] = 0ull;
         __builtin_amdgcn_wave_barrier();
         const int b = rp[v], e = rp[v + 1];
@@ -604,6 +605,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bitset(int n, const int
         for (int64_t w = lane; w < W; w += kWave) out[w] = row[w];
         __builtin_amdgcn_wave_barrier();  // the row buffer is cleared again only after every lane read it
     }
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_build_bitset(int n, const int32_t *__restrict__ rp,
+                                                                const int32_t *__restrict__ ci, uint64_t *bits,
+                                                                int64_t W)
+{
+    extern __shared__ uint64_t lds[];
+    const int wave = threadIdx.x >> 6;
+    build_rows(n, rp, ci, bits, W, lds + (int64_t)wave * W, blockIdx.x * (kBuildThreads / kWave) + wave,
+               gridDim.x * (kBuildThreads / kWave));
 }
 
 // Batch: every block first takes large graphs (whole block per graph) from a
@@ -677,6 +688,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__re
     }
     BlockTeam<T, false> tm{(int)threadIdx.x};
     tm.sync_mem();  // rank and parent of every vertex visible to the sweep
+    if (flags & kFlagOrderOnly) return;
     int G = 1, lg = 0;
     while (G < g.wn && G < kWave) {
         G <<= 1;
@@ -782,28 +794,85 @@ __global__ __launch_bounds__(kPlusScanThreads) void k_plus_scan(int n, const int
     }
 }
 
-// Renamed CSR rows: one wavefront per new row a copies the row of old
-// vertex prev[n-1-a], each neighbour u renamed to n-1-pos[u]. Entries past
-// nnz (a row_ptr that disagrees with nnz) are dropped.
+// Lanes per renamed row (log2): rows of up to 64 words get the smallest
+// power of two >= W2, at most 16, so a wavefront works on at least four
+// rows at once (four dependent loads per row make each row latency-bound);
+// longer rows get the whole wavefront.
+__host__ __device__ __forceinline__ int rename_group_log2(int W2)
+{
+    if (W2 > kWave) return 6;
+    int lg = 0;
+    while ((1 << lg) < W2 && lg < 4) ++lg;
+    return lg;
+}
+
+// LDS words of one wavefront's row buffers: (64 / G) rows of W2 words.
+__host__ __device__ __forceinline__ int rename_buffer_words(int W2) { return W2 > kWave ? W2 : 4 * kWave; }
+
+// Renamed rows of one graph, wavefront slots first, first + stride, ...,
+// each slot taking 64 / G consecutive rows (G lanes per row): row a is the
+// row of old vertex prev[n-1-a] with every neighbour u renamed to
+// n-1-pos[u], written to the renamed CSR (entries past nnz, from a row_ptr
+// that disagrees with nnz, are dropped) and, through the wavefront's LDS
+// buffer `buf` (rename_buffer_words(W2) words), to row a of the renamed
+// bitset. With `bad` (prev not a permutation) every row is empty.
+__device__ __forceinline__ void rename_rows(int n, int64_t nnz, const int32_t *prev_, const int32_t *pos_,
+                                            const int32_t *rp_, const int32_t *ci_, const int32_t *rp2_,
+                                            int32_t *ci2_, uint64_t *bits2_, int W2, bool bad, uint64_t *buf,
+                                            int first, int stride)
+{
+    LX_GLOBAL const int32_t *prev = as_global(prev_);
+    LX_GLOBAL const int32_t *pos = as_global(pos_);
+    LX_GLOBAL const int32_t *rp = as_global(rp_);
+    LX_GLOBAL const int32_t *ci = as_global(ci_);
+    LX_GLOBAL const int32_t *rp2 = as_global(rp2_);
+    LX_GLOBAL int32_t *ci2 = as_global(ci2_);
+    LX_GLOBAL uint64_t *bits2 = as_global(bits2_);
+    const int lane = threadIdx.x & 63;
+    const int lg = rename_group_log2(W2), G = 1 << lg, R = kWave >> lg;
+    const int sub = lane >> lg, gl = lane & (G - 1);
+    uint64_t *row = buf + sub * W2;  // R * W2 <= rename_buffer_words(W2)
+    for (int base = first * R; base < n; base += stride * R) {
+        const int a = base + sub;
+        for (int w = gl; w < W2; w += G) row[w] = 0ull;
+        __builtin_amdgcn_wave_barrier();
+        if (a < n && !bad) {
+            const int v = prev[n - 1 - a];
+            const int b = rp[v], e = rp[v + 1], o = rp2[a];
+            for (int j = b + gl; j < e; j += G) {
+                const int u = ci[j];
+                const int u2 = (unsigned)u < (unsigned)n ? n - 1 - pos[u] : u;
+                const int64_t q = (int64_t)o + (j - b);
+                if (q < nnz) ci2[q] = u2;
+                if ((unsigned)u2 < (unsigned)n) atomicOr((unsigned long long *)&row[u2 >> 6], 1ull << (u2 & 63));
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (a < n) {
+            LX_GLOBAL uint64_t *out = bits2 + (int64_t)a * W2;
+            for (int w = gl; w < W2; w += G) out[w] = row[w];
+        }
+        __builtin_amdgcn_wave_barrier();  // the row buffers are cleared again only after every lane read them
+    }
+}
+
+// Renamed CSR rows and bitset of one graph.
 __global__ __launch_bounds__(kPlusThreads) void k_plus_rows(int n, int64_t nnz, const int32_t *__restrict__ prev,
                                                             const int32_t *__restrict__ pos,
                                                             const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ ci,
                                                             const int32_t *__restrict__ flag,
-                                                            const int32_t *__restrict__ rp2, int32_t *ci2)
+                                                            const int32_t *__restrict__ rp2, int32_t *ci2,
+                                                            uint64_t *bits2)
 {
-    if (*flag != 0) return;
-    const int lane = threadIdx.x & 63;
-    const int stride = gridDim.x * (kPlusThreads / kWave);
-    for (int a = blockIdx.x * (kPlusThreads / kWave) + (threadIdx.x >> 6); a < n; a += stride) {
-        const int v = prev[n - 1 - a];
-        const int b = rp[v], e = rp[v + 1], o = rp2[a];
-        for (int j = b + lane; j < e; j += kWave) {
-            const int u = ci[j];
-            const int64_t q = (int64_t)o + (j - b);
-            if (q < nnz) ci2[q] = (unsigned)u < (unsigned)n ? n - 1 - pos[u] : u;
-        }
-    }
+    extern __shared__ uint64_t lds[];
+    const int W2 = (n + 63) / 64;
+    const int wave = threadIdx.x >> 6;
+    rename_rows(n, nnz, prev, pos, rp, ci, rp2, ci2, bits2, W2, *flag != 0,
+                lds + (int64_t)wave * rename_buffer_words(W2), blockIdx.x * (kPlusThreads / kWave) + wave,
+                gridDim.x * (kPlusThreads / kWave));
 }
 
 // The renamed sweep's outputs in old ids: order[i] = prev[n-1-order2[i]],
@@ -847,6 +916,10 @@ __global__ __launch_bounds__(kPlusThreads) void k_ui_check(int n, const int32_t 
     const int stride = gridDim.x * (kPlusThreads / kWave);
     for (int i = blockIdx.x * (kPlusThreads / kWave) + (threadIdx.x >> 6); i < n; i += stride) {
         const int v = order[i];
+        if ((unsigned)v >= (unsigned)n) {  // no order (the previous one was not a permutation)
+            if (lane == 0) atomicMin(key, (uint32_t)i);
+            continue;
+        }
         const int b = rp[v], e = rp[v + 1];
         uint32_t lo = (uint32_t)i, hi = (uint32_t)i;
         for (int j = b + lane; j < e; j += kWave) {
@@ -861,22 +934,19 @@ __global__ __launch_bounds__(kPlusThreads) void k_ui_check(int n, const int32_t 
     }
 }
 
-// Verdict and witness. For the failing vertex v of smallest position i, with
-// [lo, hi] the span of N[v]: b is the earliest vertex in the span that is not
-// in N[v], and the triple is (order[lo], b, v) when b comes before v, else
-// (v, b, order[hi]): its first and last vertices are adjacent, the middle one
-// is not adjacent to both.
-__global__ __launch_bounds__(kFinishThreads) void k_ui_witness(int n, const int32_t *__restrict__ rp,
-                                                               const int32_t *__restrict__ ci,
-                                                               const uint64_t *__restrict__ bits, int64_t W,
-                                                               const int32_t *__restrict__ order,
-                                                               const int32_t *__restrict__ rank,
-                                                               const uint32_t *__restrict__ key,
-                                                               lexbfs_interval_result_t *res)
+// Verdict and witness of one graph on one workgroup, `i` the smallest
+// failing position (kNoFail if none). For the failing vertex v at position
+// i, with [lo, hi] the span of N[v]: b is the earliest vertex in the span
+// that is not in N[v], and the triple is (order[lo], b, v) when b comes
+// before v, else (v, b, order[hi]): its first and last vertices are
+// adjacent, the middle one is not adjacent to both.
+template <int T>
+__device__ void ui_witness_block(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                 const uint64_t *__restrict__ bits, int64_t W, const int32_t *__restrict__ order,
+                                 const int32_t *__restrict__ rank, uint32_t i, lexbfs_interval_result_t *res,
+                                 uint32_t *red)
 {
-    __shared__ uint32_t red[kFinishThreads / kWave];
     const int t = threadIdx.x;
-    const uint32_t i = *key;
     if (i == kNoFail) {
         if (t == 0) {
             res->unit_interval = 1;
@@ -885,11 +955,19 @@ __global__ __launch_bounds__(kFinishThreads) void k_ui_witness(int n, const int3
         }
         return;
     }
-    BlockTeam<kFinishThreads, false> tm{t};
+    BlockTeam<T, false> tm{t};
     const int v = order[i];
+    if ((unsigned)v >= (unsigned)n) {
+        if (t == 0) {
+            res->unit_interval = 0;
+            res->witness[0] = res->witness[1] = res->witness[2] = -1;
+            for (int k = 0; k < 4; ++k) res->reserved[k] = 0;
+        }
+        return;
+    }
     const int b = rp[v], e = rp[v + 1];
     uint32_t lo = i, hi = i;
-    for (int j = b + t; j < e; j += kFinishThreads) {
+    for (int j = b + t; j < e; j += T) {
         const int u = ci[j];
         const uint32_t r = (unsigned)u < (unsigned)n ? (uint32_t)rank[u] : (uint32_t)n;
         lo = min(lo, r);
@@ -899,7 +977,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_ui_witness(int n, const int3
     hi = min(~tm.min_all(~hi, red), (uint32_t)n - 1);  // positions stay inside the order
     const uint64_t *row = bits + (int64_t)v * W;
     uint32_t cand = kNoFail;  // the first position of this lane's stride that is outside N[v]
-    for (uint32_t p = lo + t; p <= hi; p += kFinishThreads)
+    for (uint32_t p = lo + t; p <= hi; p += T)
         if (p != i && !test_bit(row, order[p])) {
             cand = p;
             break;
@@ -920,6 +998,162 @@ __global__ __launch_bounds__(kFinishThreads) void k_ui_witness(int n, const int3
         }
         for (int k = 0; k < 4; ++k) res->reserved[k] = 0;
     }
+}
+
+__global__ __launch_bounds__(kFinishThreads) void k_ui_witness(int n, const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               const uint64_t *__restrict__ bits, int64_t W,
+                                                               const int32_t *__restrict__ order,
+                                                               const int32_t *__restrict__ rank,
+                                                               const uint32_t *__restrict__ key,
+                                                               lexbfs_interval_result_t *res)
+{
+    __shared__ uint32_t red[kFinishThreads / kWave];
+    ui_witness_block<kFinishThreads>(n, rp, ci, bits, W, order, rank, *key, res, red);
+}
+
+// ---------------------------------------------------------------------------
+// Batched unit interval test: the same steps for many graphs, each kernel
+// covering the whole batch (a workgroup, or a row of workgroups, per graph);
+// the three LexBFS passes are batch plans over the original and the renamed
+// graphs.
+// ---------------------------------------------------------------------------
+struct IDesc {
+    int32_t n;
+    int32_t wn;         // ceil(n / 64): row stride of the renamed bitset
+    int64_t nnz;
+    int64_t W;          // row stride of the input bitset
+    const int32_t *rp;
+    const int32_t *ci;
+    const uint64_t *bits;
+    int32_t *rp2;       // renamed CSR [n+1], [nnz] and bitset [n * wn]
+    int32_t *ci2;
+    uint64_t *bits2;
+    int32_t *pos;       // [n] position in the previous order
+    int32_t *s1;        // the three orders [n] and the ranks of the third
+    int32_t *s2;
+    int32_t *s3;
+    int32_t *rank3;
+    int32_t *flag;      // [1] previous order not a permutation
+    uint32_t *key;      // [1] smallest failing position of the third order
+    lexbfs_interval_result_t *res;
+};
+
+constexpr int kIbThreads = 256;
+
+// Renaming of one graph per workgroup after prev = s1 (sel 1) or s2 (sel 2):
+// inverse and validity, renamed row lengths and their prefix sum -- the
+// single-graph kernels' steps, ordered by workgroup barriers.
+__global__ __launch_bounds__(kIbThreads) void k_ib_rename(const IDesc *__restrict__ ds, int sel)
+{
+    __shared__ int s_bad;
+    __shared__ uint32_t red[kIbThreads / kWave];
+    const IDesc d = ds[blockIdx.x];
+    const int n = d.n;
+    if (n == 0) return;
+    const int32_t *prev = sel == 2 ? d.s2 : d.s1;
+    const int t = threadIdx.x;
+    if (t == 0) s_bad = 0;
+    for (int v = t; v < n; v += kIbThreads) d.pos[v] = -1;
+    __syncthreads();
+    for (int i = t; i < n; i += kIbThreads) {
+        const int v = prev[i];
+        if ((unsigned)v >= (unsigned)n || atomicExch(&d.pos[v], i) != -1) atomicOr(&s_bad, 1);
+    }
+    __syncthreads();
+    const bool bad = s_bad != 0;
+    if (t == 0) *d.flag = bad ? 1 : 0;
+    for (int a = t; a < n; a += kIbThreads) {
+        int deg = 0;
+        if (!bad) {
+            const int v = prev[n - 1 - a];
+            deg = d.rp[v + 1] - d.rp[v];
+        }
+        d.rp2[a + 1] = deg;
+    }
+    __syncthreads();
+    const int per = (n + kIbThreads - 1) / kIbThreads;
+    const int a0 = min(n, t * per), a1 = min(n, a0 + per);
+    uint32_t sum = 0;
+    for (int a = a0; a < a1; ++a) sum += (uint32_t)d.rp2[a + 1];
+    BlockTeam<kIbThreads, false> tm{t};
+    uint32_t off = tm.exclusive_scan(sum, red);
+    for (int a = a0; a < a1; ++a) {
+        off += (uint32_t)d.rp2[a + 1];
+        d.rp2[a + 1] = (int32_t)off;
+    }
+    if (t == 0) d.rp2[0] = 0;
+}
+
+// Renamed CSR rows and bitsets: graph blockIdx.x, rows spread over the
+// gridDim.y workgroups of its grid row; `bufw` LDS words per wavefront
+// (rename_buffer_words of the widest row).
+__global__ __launch_bounds__(kBuildThreads) void k_ib_rows(const IDesc *__restrict__ ds, int sel, int bufw)
+{
+    extern __shared__ uint64_t lds[];
+    const IDesc d = ds[blockIdx.x];
+    const int wave = threadIdx.x >> 6;
+    rename_rows(d.n, d.nnz, sel == 2 ? d.s2 : d.s1, d.pos, d.rp, d.ci, d.rp2, d.ci2, d.bits2, d.wn, *d.flag != 0,
+                lds + (int64_t)wave * bufw, blockIdx.y * (kBuildThreads / kWave) + wave,
+                gridDim.y * (kBuildThreads / kWave));
+}
+
+// The renamed pass's order in old ids: s2 from s1 (sel 2) or s3 and its
+// ranks from s2 (sel 3, which also resets the failure key).
+__global__ __launch_bounds__(kIbThreads) void k_ib_map(const IDesc *__restrict__ ds, const GDesc *__restrict__ renamed,
+                                                       int sel)
+{
+    const IDesc d = ds[blockIdx.x];
+    const int n = d.n;
+    if (sel == 3 && threadIdx.x == 0) *d.key = kNoFail;
+    if (n == 0) return;
+    const int32_t *prev = sel == 2 ? d.s1 : d.s2;
+    int32_t *out = sel == 2 ? d.s2 : d.s3;
+    int32_t *rank = sel == 3 ? d.rank3 : nullptr;
+    const int32_t *order2 = renamed[blockIdx.x].order;
+    const bool bad = *d.flag != 0;
+    for (int i = threadIdx.x; i < n; i += kIbThreads) {
+        const int a = order2[i];
+        if (bad || (unsigned)a >= (unsigned)n) {
+            out[i] = -1;
+            if (rank) rank[i] = -1;
+            continue;
+        }
+        const int v = prev[n - 1 - a];
+        out[i] = v;
+        if (rank) rank[v] = i;
+    }
+}
+
+// Consecutive-neighbourhood check: graph blockIdx.x, one lane per position,
+// positions spread over the gridDim.y workgroups of the grid row.
+__global__ __launch_bounds__(kIbThreads) void k_ib_check(const IDesc *__restrict__ ds)
+{
+    const IDesc d = ds[blockIdx.x];
+    const int n = d.n;
+    for (int i = blockIdx.y * kIbThreads + threadIdx.x; i < n; i += gridDim.y * kIbThreads) {
+        const int v = d.s3[i];
+        if ((unsigned)v >= (unsigned)n) {  // no order (the previous one was not a permutation)
+            atomicMin(d.key, (uint32_t)i);
+            continue;
+        }
+        const int b = d.rp[v], e = d.rp[v + 1];
+        uint32_t lo = (uint32_t)i, hi = (uint32_t)i;
+        for (int j = b; j < e; ++j) {
+            const int u = d.ci[j];
+            const uint32_t r = (unsigned)u < (unsigned)n ? (uint32_t)d.rank3[u] : (uint32_t)n;
+            lo = min(lo, r);
+            hi = max(hi, r);
+        }
+        if (hi - lo != (uint32_t)(e - b)) atomicMin(d.key, (uint32_t)i);
+    }
+}
+
+__global__ __launch_bounds__(kIbThreads) void k_ib_witness(const IDesc *__restrict__ ds)
+{
+    __shared__ uint32_t red[kIbThreads / kWave];
+    const IDesc d = ds[blockIdx.x];
+    ui_witness_block<kIbThreads>(d.n, d.rp, d.ci, d.bits, d.W, d.s3, d.rank3, *d.key, d.res, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1300,11 +1534,11 @@ int plus_sweep(const lexbfs_graph_t *g, const int32_t *prev, int32_t *order, int
                            n, npad, prev, g->row_ptr, (const int32_t *)flag, deg);
         hipLaunchKernelGGL(k_plus_scan, dim3(1), dim3(kPlusScanThreads), 0, s, n, (const int32_t *)deg, rp2);
         const int rblocks = std::max(1, std::min((n + 3) / 4, cus * 8));
-        hipLaunchKernelGGL(k_plus_rows, dim3(rblocks), dim3(kPlusThreads), 0, s, n, g->nnz, prev, (const int32_t *)pos,
-                           g->row_ptr, g->col_idx, (const int32_t *)flag, (const int32_t *)rp2, ci2);
+        const size_t rlds = (size_t)(kPlusThreads / kWave) * 8 * (size_t)rename_buffer_words((n + 63) / 64);
+        hipLaunchKernelGGL(k_plus_rows, dim3(rblocks), dim3(kPlusThreads), rlds, s, n, g->nnz, prev,
+                           (const int32_t *)pos, g->row_ptr, g->col_idx, (const int32_t *)flag, (const int32_t *)rp2,
+                           ci2, bits2);
         LX_CHECK_LAUNCH("LexBFS+ renaming launches");
-        const int rc = launch_build_bitset(n, rp2, ci2, bits2, (n + 63) / 64, s);
-        if (rc) return rc;
     }
     lexbfs_graph_t g2;
     g2.n = n;
@@ -1524,7 +1758,7 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
     lexbfs_batch_plan_t *P = new (std::nothrow) lexbfs_batch_plan_t();
     if (!P) return fail_code(LEXBFS_EINVAL, "out of host memory for the batch plan");
     P->count = count;
-    P->flags = flags;
+    P->flags = flags & ~kFlagOrderOnly;
     P->ws = (char *)ws;
     P->L = L;
     char *w = (char *)ws;
@@ -1614,6 +1848,140 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
     *plan_out = P;
     return LEXBFS_OK;
 }
+// Workspace of a batched unit interval test: two batch plans (original and
+// renamed graphs, same sizes), scratch verdicts of the plans, the interval
+// descriptors, then per graph its three orders, ranks, pos, renamed CSR and
+// bitset, flag and key.
+struct UiBatchWs {
+    BatchWs plan;
+    size_t planA, planB, pres, idesc, total;
+    std::vector<size_t> graph;
+};
+
+size_t ui_graph_bytes(int n, int64_t nnz)
+{
+    const size_t m = (size_t)std::max(n, 1);
+    return 5 * al(m * 4) + al((m + 1) * 4) + al((size_t)std::max<int64_t>(nnz, 1) * 4) + al(m * ((m + 63) / 64) * 8) +
+           kAlign;
+}
+
+// (Fills U rather than returning it: this part of the file has C linkage.)
+void ui_batch_layout(const lexbfs_graph_t *gs, int32_t count, UiBatchWs &U)
+{
+    U.plan = batch_layout(gs, count);
+    size_t off = 0;
+    U.planA = off; off += U.plan.total;
+    U.planB = off; off += U.plan.total;
+    U.pres = off; off += al(sizeof(lexbfs_result_t) * (size_t)count);
+    U.idesc = off; off += al(sizeof(IDesc) * (size_t)count);
+    U.graph.resize(count);
+    for (int i = 0; i < count; ++i) {
+        U.graph[i] = off;
+        off += ui_graph_bytes(gs[i].n, gs[i].nnz);
+    }
+    U.total = off;
+}
+
+// Owns the two plans of one batched call.
+struct PlanPair {
+    lexbfs_batch_plan_t *a = nullptr, *b = nullptr;
+    ~PlanPair()
+    {
+        delete a;
+        delete b;
+    }
+};
+
+int ui_batch_run(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result_t *res, int32_t *const *orders,
+                 char *w, const UiBatchWs &U, hipStream_t s)
+{
+    std::vector<IDesc> hd(count);
+    std::vector<lexbfs_graph_t> g2(count);
+    std::vector<lexbfs_outputs_t> oa(count);
+    int maxn = 0, maxw = 1;
+    for (int i = 0; i < count; ++i) {
+        const lexbfs_graph_t &g = gs[i];
+        const size_t m = (size_t)std::max(g.n, 1);
+        const size_t a = al(m * 4);
+        char *p = w + U.graph[i];
+        IDesc &d = hd[i];
+        d.n = g.n;
+        d.wn = (g.n + 63) / 64;
+        d.nnz = g.nnz;
+        d.W = g.words_per_row;
+        d.rp = g.row_ptr;
+        d.ci = g.col_idx;
+        d.bits = g.bits;
+        d.s1 = (int32_t *)p; p += a;
+        d.s2 = (int32_t *)p; p += a;
+        d.s3 = (orders && orders[i]) ? orders[i] : (int32_t *)p; p += a;
+        d.rank3 = (int32_t *)p; p += a;
+        d.pos = (int32_t *)p; p += a;
+        d.rp2 = (int32_t *)p; p += al((m + 1) * 4);
+        d.ci2 = (int32_t *)p; p += al((size_t)std::max<int64_t>(g.nnz, 1) * 4);
+        d.bits2 = (uint64_t *)p; p += al(m * ((m + 63) / 64) * 8);
+        d.flag = (int32_t *)p;
+        d.key = (uint32_t *)(p + 4);
+        d.res = res + i;
+        lexbfs_graph_t &r = g2[i];
+        r.n = g.n;
+        r.reserved = 0;
+        r.nnz = g.nnz;
+        r.row_ptr = d.rp2;
+        r.col_idx = d.ci2;
+        r.bits = d.bits2;
+        r.words_per_row = std::max(d.wn, 1);
+        oa[i].order = d.s1;
+        oa[i].rank = oa[i].parent = oa[i].cycle = nullptr;
+        maxn = std::max(maxn, g.n);
+        maxw = std::max(maxw, d.wn);
+    }
+    lexbfs_result_t *pres = (lexbfs_result_t *)(w + U.pres);
+    PlanPair pp;
+    int rc = plan_create(gs, count, oa.data(), pres, nullptr, w + U.planA, U.plan.total, 0, s, false, &pp.a);
+    if (rc) return rc;
+    rc = plan_create(g2.data(), count, nullptr, pres, nullptr, w + U.planB, U.plan.total, 0, s, false, &pp.b);
+    if (rc) return rc;
+    pp.a->flags |= kFlagOrderOnly;
+    pp.b->flags |= kFlagOrderOnly;
+    const IDesc *dd = (const IDesc *)(w + U.idesc);
+    const hipError_t e = hipMemcpyAsync(w + U.idesc, hd.data(), sizeof(IDesc) * (size_t)count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e, "staging the interval descriptors");
+    const GDesc *renamed = (const GDesc *)(w + U.planB + U.plan.gds);
+    const int spread = std::max(1, 65536 / count);  // workgroups per graph for the row-parallel kernels
+    const int ybits = std::max(1, std::min((maxn + 63) / 64, spread));
+    const int ycheck = std::max(1, std::min((maxn + kIbThreads - 1) / kIbThreads, spread));
+    rc = lexbfs_batch_plan_launch(pp.a, s);
+    if (rc) return rc;
+    for (int sel = 1; sel <= 2; ++sel) {
+        {
+            ProfScope ps(3, s);
+            hipLaunchKernelGGL(k_ib_rename, dim3(count), dim3(kIbThreads), 0, s, dd, sel);
+            const int bufw = rename_buffer_words(maxw);
+            hipLaunchKernelGGL(k_ib_rows, dim3(count, ybits), dim3(kBuildThreads),
+                               (size_t)(kBuildThreads / kWave) * 8 * (size_t)bufw, s, dd, sel, bufw);
+        }
+        LX_CHECK_LAUNCH("batched LexBFS+ renaming launches");
+        rc = lexbfs_batch_plan_launch(pp.b, s);
+        if (rc) return rc;
+        {
+            ProfScope ps(3, s);
+            hipLaunchKernelGGL(k_ib_map, dim3(count), dim3(kIbThreads), 0, s, dd, renamed, sel + 1);
+        }
+        LX_CHECK_LAUNCH("batched LexBFS+ order launch");
+    }
+    {
+        ProfScope ps(1, s);
+        hipLaunchKernelGGL(k_ib_check, dim3(count, ycheck), dim3(kIbThreads), 0, s, dd);
+    }
+    {
+        ProfScope ps(2, s);
+        hipLaunchKernelGGL(k_ib_witness, dim3(count), dim3(kIbThreads), 0, s, dd);
+    }
+    LX_CHECK_LAUNCH("batched interval check launches");
+    return LEXBFS_OK;
+}
+
 }  // namespace
 
 int lexbfs_batch_plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,
@@ -1760,6 +2128,29 @@ int unit_interval_test(const lexbfs_graph_t *g, lexbfs_interval_result_t *res, i
     }
     LX_CHECK_LAUNCH("interval witness launch");
     return LEXBFS_OK;
+}
+
+size_t unit_interval_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
+{
+    if (!gs || count <= 0) return kAlign;
+    UiBatchWs U;
+    ui_batch_layout(gs, count, U);
+    return U.total;
+}
+
+int unit_interval_test_batch(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result_t *res,
+                             int32_t *const *orders, void *ws, size_t ws_bytes, void *stream)
+{
+    if (count < 0 || (count > 0 && (!gs || !res))) return LEXBFS_EINVAL;
+    if (count == 0) return LEXBFS_OK;
+    for (int i = 0; i < count; ++i) {
+        const int rc = validate_graph(&gs[i]);
+        if (rc) return rc;
+    }
+    UiBatchWs U;
+    ui_batch_layout(gs, count, U);
+    if (!ws || ws_bytes < U.total) return LEXBFS_ENOWS;
+    return ui_batch_run(gs, count, res, orders, (char *)ws, U, (hipStream_t)stream);
 }
 
 int32_t lexbfs_batch_max_n(void)

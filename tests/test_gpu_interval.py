@@ -121,3 +121,53 @@ def test_workspace_and_stream_reuse():
         raw = r.res_raw.tolist()
         assert bool(raw[0]) == ref.unit_interval and tuple(raw[1:4]) == ref.witness, g.name
         assert np.array_equal(r.order.cpu().numpy(), ref.order), g.name
+
+
+def check_batch(graphs, tag, outputs=True):
+    say(f"[interval batch] {tag} count={len(graphs)} sum_n={sum(g.n for g in graphs)}")
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.unit_interval_test_batch(dgs, outputs=outputs)
+    for g, r in zip(graphs, rs):
+        ref = oracle.unit_interval_test(g)
+        assert r.unit_interval == ref.unit_interval, f"verdict {g.name}"
+        assert r.witness == ref.witness, f"witness {g.name}: {r.witness} vs {ref.witness}"
+        if outputs:
+            assert np.array_equal(r.order.cpu().numpy(), ref.order), f"third order {g.name}"
+        assert r.res_raw[4:].tolist() == [0, 0, 0, 0]
+    return rs
+
+
+def test_batch_mix():
+    """Mixed sizes and kinds, with empty, one-vertex and structured graphs:
+    wavefront and workgroup teams in the same passes."""
+    graphs = gg.config_interval_batch(count=150, lo=32, hi=4096, seed=3)
+    graphs += [gg.from_edges(0, []), gg.from_edges(1, []), gg.from_edges(6, [(i, (i + 1) % 6) for i in range(6)])]
+    graphs += structured_cases()[::5]
+    check_batch(graphs, "mix")
+
+
+def test_batch_large_tier():
+    """Graphs above lexbfs_batch_max_n() run on the 1024-lane tier."""
+    big = lx._lib.load().lexbfs_batch_max_n() + 500
+    graphs = [gg.intervals(big, 10, 21), gg.intervals(big + 7, 10, 22, unit=False), gg.intervals(700, 8, 23)]
+    check_batch(graphs, f"large tier n={big}")
+
+
+def test_batch_equals_single():
+    graphs = gg.config_interval_batch(count=40, lo=64, hi=2048, seed=5)
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.unit_interval_test_batch(dgs, outputs=True)
+    for d, r in zip(dgs, rs):
+        one = lx.unit_interval_test(d)
+        assert one.unit_interval == r.unit_interval and one.witness == r.witness
+        assert torch.equal(one.order, r.order)
+
+
+def test_batch_full_workload():
+    """The benchmark's 4,096-graph interval batch, every verdict and witness
+    against the oracle; the third orders on an evenly spaced sample."""
+    graphs = gg.config_interval_batch()
+    rs = check_batch(graphs, "N log-uniform [32, 4096] x 4096", outputs=False)
+    assert sum(r.unit_interval for r in rs) > 0
+    sample = graphs[::64]
+    check_batch(sample, "sample with orders")
