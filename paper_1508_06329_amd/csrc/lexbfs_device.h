@@ -521,6 +521,16 @@ __device__ __forceinline__ LdsLayoutG carve_lds_g(void *base, int n, int team)
     return L;
 }
 
+// Which of 8 consecutive 16-bit class ids (one 16-byte LDS read) equal c:
+// bit j for entry j.
+__device__ __forceinline__ uint32_t match8(uint4 q, uint32_t c)
+{
+    const uint32_t pat = c | (c << 16);
+    const uint32_t x0 = q.x ^ pat, x1 = q.y ^ pat, x2 = q.z ^ pat, x3 = q.w ^ pat;
+    return ((x0 & 0xFFFFu) == 0) | ((x0 >> 16) == 0) << 1 | ((x1 & 0xFFFFu) == 0) << 2 | ((x1 >> 16) == 0) << 3 |
+           ((x2 & 0xFFFFu) == 0) << 4 | ((x2 >> 16) == 0) << 5 | ((x3 & 0xFFFFu) == 0) << 6 | ((x3 >> 16) == 0) << 7;
+}
+
 // Bits of my unnumbered vertices `um` (word positions) whose class is c.
 __device__ __forceinline__ uint64_t chunk_match(const uint16_t *cls, uint64_t um, uint32_t c, int vbase, int sh, int K)
 {
@@ -640,6 +650,23 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         U -= 1;
         const uint32_t stop = Tabs::kInLds ? xcls : (uint32_t)cls[x];
         const bool gone = (int)stop == U;  // x was the last member of the top class
+        // What the gone case reads, loaded now, in the shadow of the pivot
+        // row: the two class-start words at and below position U - 1 and the
+        // class ids of my chunk (K = 8 or 16). Nothing changes them before the
+        // case uses them: phase A writes neither, and the class start cleared
+        // below is U, above U - 1.
+        uint64_t s_hi = 0ull, s_lo = 0ull;
+        uint4 c_lo = make_uint4(0u, 0u, 0u, 0u), c_hi = make_uint4(0u, 0u, 0u, 0u);
+        if (gone && U > 0) {
+            const int pw = (U - 1) >> 6;
+            s_hi = starts[pw];
+            if (pw > 0) s_lo = starts[pw - 1];
+            if ((K == 8 || K == 16) && owner) {
+                const uint4 *p = (const uint4 *)(cls + vbase);
+                c_lo = p[0];
+                if (K == 16 && vbase + 8 < n) c_hi = p[1];
+            }
+        }
         if (owner && (x >> 6) == (uint32_t)wi) {
             um &= ~(1ull << (x & 63));
             top &= ~(1ull << (x & 63));
@@ -694,8 +721,11 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         if (gone) {
             const uint32_t pos = (uint32_t)(U - 1);
             int w = (int)(pos >> 6);
-            uint64_t sw = starts[w] & (~0ull >> (63 - (pos & 63)));
-            if (!sw && w > 0) sw = starts[--w];
+            uint64_t sw = s_hi & (~0ull >> (63 - (pos & 63)));
+            if (!sw && w > 0) {
+                sw = s_lo;
+                --w;
+            }
             if (sw) {
                 cand = ((uint32_t)w << 6) | (uint32_t)(63 - __builtin_clzll(sw));
             } else {
@@ -707,7 +737,9 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
                 cand = tm.max_all(hi, red + par * 2 * NW) - 1u;
                 par ^= 1;
             }
-            top = chunk_match(cls, um, cand, vbase, sh, K);
+            if (K == 16) top = ((uint64_t)(match8(c_lo, cand) | match8(c_hi, cand) << 8) << sh) & um;
+            else if (K == 8) top = ((uint64_t)match8(c_lo, cand) << sh) & um;
+            else top = chunk_match(cls, um, cand, vbase, sh, K);
         }
         // One reduction: the selection key (max) and two 16-bit sums packed
         // in one word -- the candidate class's neighbour count and x's
