@@ -379,8 +379,8 @@ def bench_interval(args):
                    "sum_m": sum(g.m for g in graphs), "parallelism": "1 GPU"},
         "unit_interval_graphs": int(sum(int(x) for x in got[:, 0])),
         "roofline": {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "avg_launch_ms": d["avg_ms"],
-                     "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
+                     "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dom), "kernel": dom,
+                     "avg_launch_ms": d["avg_ms"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
         "kernels": per_kind,
         "per_graph": per_graph,
         "cpu_baseline": cpu,
