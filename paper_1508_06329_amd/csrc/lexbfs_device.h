@@ -1131,6 +1131,7 @@ __device__ __forceinline__ void sweep_rows(const uint64_t *bits_, int64_t W, int
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (gid * G));
+    uint32_t best = kNoFail;  // smallest failing rank among this lane group's rows
     for (int vb = r0 + wave * gpw; vb < r1; vb += nwaves * gpw) {
         const int v = vb + gid;
         bool fail = false;
@@ -1142,20 +1143,41 @@ __device__ __forceinline__ void sweep_rows(const uint64_t *bits_, int64_t W, int
                 const int rp = rank[p];
                 LX_GLOBAL const uint64_t *a = bits + (int64_t)v * W;
                 LX_GLOBAL const uint64_t *b = bits + (int64_t)p * W;
-                for (int w = gl; w < wn && !fail; w += G) {
-                    uint64_t X = __builtin_nontemporal_load(a + w) & ~b[w];
-                    if (w == wn - 1) X &= tail;  // ids >= n never index rank[]
-                    while (X) {
-                        const int z = (w << 6) + ctz64(X);
-                        X &= X - 1;
-                        if (rank[z] < rp) { fail = true; break; }
+                // Eight words of both rows per lane in flight before any is
+                // tested (the early exit would otherwise serialise the loads).
+                for (int w0 = gl; w0 < wn && !fail; w0 += 8 * G) {
+                    // Addresses clamped to the last word rather than loads
+                    // made conditional: conditional loads compile to branches
+                    // that each wait for the loads before them.
+                    uint64_t A[8], B[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int w = min(w0 + u * G, wn - 1);
+                        A[u] = __builtin_nontemporal_load(a + w);
+                        B[u] = b[w];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int w = w0 + u * G;
+                        uint64_t X = w < wn ? A[u] & ~B[u] : 0ull;
+                        if (w == wn - 1) X &= tail;  // ids >= n never index rank[]
+                        while (X && !fail) {
+                            const int z = (w << 6) + ctz64(X);
+                            X &= X - 1;
+                            if (rank[z] < rp) fail = true;
+                        }
                     }
                 }
             }
         }
         const uint64_t bal = __ballot(fail);
-        if ((bal & gmask) && gl == 0) __hip_atomic_fetch_min(failkey, (uint32_t)rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bal & gmask) best = min(best, (uint32_t)rv);
     }
+    // One atomic per wavefront: in a graph where most rows fail, one per
+    // failing row would queue thousands of atomics on a single L2 word.
+    best = wave_min_u32(best);
+    if (lane == 0 && best != kNoFail)
+        __hip_atomic_fetch_min(failkey, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
