@@ -139,3 +139,44 @@ def test_python_constants_match_header():
             assert getattr(_lib, name) == int(val, 0), name
             checked += 1
     assert checked >= 8 and "LEXBFS_FLAG_PER_STEP" in defs
+
+
+def test_multi_sweep_argument_errors(lib):
+    """LexBFS+ and the unit interval test reject bad arguments before any
+    device work (the pointers below are never dereferenced)."""
+    g = fake_graph(100)
+    need = lib.lexbfs_plus_workspace_bytes(100, g.nnz)
+    prev, order, ws, res = 0x40000, 0x50000, 0x60000, 0x70000
+    assert need > lib.lexbfs_plus_workspace_bytes(50, g.nnz) > 0
+    assert lib.lexbfs_plus_order(None, prev, order, None, None, ws, need, None) == _lib.LEXBFS_EINVAL
+    assert lib.lexbfs_plus_order(ctypes.byref(g), None, order, None, None, ws, need, None) == _lib.LEXBFS_EINVAL
+    assert lib.lexbfs_plus_order(ctypes.byref(g), prev, None, None, None, ws, need, None) == _lib.LEXBFS_EINVAL
+    assert lib.lexbfs_plus_order(ctypes.byref(g), prev, order, None, None, ws, need - 1, None) == _lib.LEXBFS_ENOWS
+    assert lib.lexbfs_plus_order(ctypes.byref(g), prev, order, None, None, None, need, None) == _lib.LEXBFS_ENOWS
+    big = fake_graph(_lib.LEXBFS_MAX_N + 1)
+    assert lib.lexbfs_plus_order(ctypes.byref(big), prev, order, None, None, ws, 1 << 40, None) == _lib.LEXBFS_ETOOBIG
+    empty = fake_graph(0, nnz=0)
+    assert lib.lexbfs_plus_order(ctypes.byref(empty), None, None, None, None, None, 0, None) == _lib.LEXBFS_OK
+    # the bitset is not needed for a LexBFS+ sweep
+    nobits = fake_graph(100)
+    nobits.bits = None
+    assert lib.lexbfs_plus_order(ctypes.byref(nobits), prev, order, None, None, ws, need - 1, None) == _lib.LEXBFS_ENOWS
+
+    uneed = lib.unit_interval_workspace_bytes(100, g.nnz)
+    assert uneed > need
+    assert lib.unit_interval_test(ctypes.byref(g), None, None, ws, uneed, None) == _lib.LEXBFS_EINVAL
+    assert lib.unit_interval_test(ctypes.byref(g), res, None, ws, uneed - 1, None) == _lib.LEXBFS_ENOWS
+    assert lib.unit_interval_test(ctypes.byref(nobits), res, None, ws, uneed, None) == _lib.LEXBFS_EINVAL
+    bad = fake_graph(100)
+    bad.reserved = 3
+    assert lib.unit_interval_test(ctypes.byref(bad), res, None, ws, uneed, None) == _lib.LEXBFS_EINVAL
+
+    arr = (_lib.lexbfs_graph_t * 2)(fake_graph(10), fake_graph(20))
+    bneed = lib.unit_interval_batch_workspace_bytes(arr, 2)
+    assert bneed > 0 and lib.unit_interval_batch_workspace_bytes(None, 0) > 0
+    assert lib.unit_interval_test_batch(arr, 2, None, None, ws, bneed, None) == _lib.LEXBFS_EINVAL
+    assert lib.unit_interval_test_batch(arr, -1, res, None, ws, bneed, None) == _lib.LEXBFS_EINVAL
+    assert lib.unit_interval_test_batch(arr, 0, None, None, None, 0, None) == _lib.LEXBFS_OK
+    assert lib.unit_interval_test_batch(arr, 2, res, None, ws, bneed - 1, None) == _lib.LEXBFS_ENOWS
+    arr = (_lib.lexbfs_graph_t * 2)(fake_graph(10), fake_graph(70000))
+    assert lib.unit_interval_test_batch(arr, 2, res, None, ws, 1 << 40, None) == _lib.LEXBFS_ETOOBIG
