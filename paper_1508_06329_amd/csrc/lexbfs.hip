@@ -112,6 +112,7 @@ struct GDesc {
     uint32_t *failkey; // [1]
     uint32_t *gtab;    // [2n] class tables in global memory (large n), else null
     lexbfs_result_t *res;
+    int32_t ilv;       // 1: ties go to the smallest interleaved rank (ilv_rank), not id
 };
 
 // ---------------------------------------------------------------------------
@@ -564,7 +565,7 @@ __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32
     } else {
         BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
         lexbfs_team<Team, LdsTables<true>, true>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, B.L.starts,
-                                                  B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
+                                                  B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp, g.ilv != 0);
     }
     tm.sync_mem();  // order, rank, parent and the failing rank visible to the team
     if (!(flags & kFlagOrderOnly)) finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
@@ -794,6 +795,26 @@ __global__ __launch_bounds__(kPlusScanThreads) void k_plus_scan(int n, const int
     }
 }
 
+// New ids of a renamed graph against tie ranks (the previous order
+// reversed): equal when K = 0, else the interleaved order of a team with K
+// vertices per lane (ilv_rank / ilv_id).
+struct IlvMap {
+    uint32_t K, lgK, tl, cl;
+    __device__ IlvMap(int n, int k) : K((uint32_t)k), lgK(0), tl(0), cl(0)
+    {
+        if (K) {
+            while ((1u << lgK) < K) ++lgK;
+            tl = (uint32_t)(n - 1) >> lgK;
+            cl = (uint32_t)n - (tl << lgK);
+        }
+    }
+    __device__ __forceinline__ uint32_t rank_of(uint32_t a) const
+    {
+        return K ? ilv_rank(a & (K - 1), a >> lgK, tl, cl) : a;
+    }
+    __device__ __forceinline__ uint32_t id_of(uint32_t r) const { return K ? ilv_id(r, tl, cl, K) : r; }
+};
+
 // Lanes per renamed row (log2): rows of up to 64 words get the smallest
 // power of two >= W2, at most 16, so a wavefront works on at least four
 // rows at once (four dependent loads per row make each row latency-bound);
@@ -811,16 +832,18 @@ __host__ __device__ __forceinline__ int rename_buffer_words(int W2) { return W2 
 
 // Renamed rows of one graph, wavefront slots first, first + stride, ...,
 // each slot taking 64 / G consecutive rows (G lanes per row): row a is the
-// row of old vertex prev[n-1-a] with every neighbour u renamed to
-// n-1-pos[u], written to the renamed CSR (entries past nnz, from a row_ptr
+// row of old vertex prev[n-1-rank(a)] with every neighbour u renamed to
+// id(n-1-pos[u]) (rank and id of IlvMap, identities when ik = 0), written
+// to the renamed CSR (entries past nnz, from a row_ptr
 // that disagrees with nnz, are dropped) and, through the wavefront's LDS
 // buffer `buf` (rename_buffer_words(W2) words), to row a of the renamed
 // bitset. With `bad` (prev not a permutation) every row is empty.
 __device__ __forceinline__ void rename_rows(int n, int64_t nnz, const int32_t *prev_, const int32_t *pos_,
                                             const int32_t *rp_, const int32_t *ci_, const int32_t *rp2_,
                                             int32_t *ci2_, uint64_t *bits2_, int W2, bool bad, uint64_t *buf,
-                                            int first, int stride)
+                                            int first, int stride, int ik = 0)
 {
+    const IlvMap map(n, ik);
     LX_GLOBAL const int32_t *prev = as_global(prev_);
     LX_GLOBAL const int32_t *pos = as_global(pos_);
     LX_GLOBAL const int32_t *rp = as_global(rp_);
@@ -837,11 +860,11 @@ __device__ __forceinline__ void rename_rows(int n, int64_t nnz, const int32_t *p
         for (int w = gl; w < W2; w += G) row[w] = 0ull;
         __builtin_amdgcn_wave_barrier();
         if (a < n && !bad) {
-            const int v = prev[n - 1 - a];
+            const int v = prev[n - 1 - (int)map.rank_of((uint32_t)a)];
             const int b = rp[v], e = rp[v + 1], o = rp2[a];
             for (int j = b + gl; j < e; j += G) {
                 const int u = ci[j];
-                const int u2 = (unsigned)u < (unsigned)n ? n - 1 - pos[u] : u;
+                const int u2 = (unsigned)u < (unsigned)n ? (int)map.id_of((uint32_t)(n - 1 - pos[u])) : u;
                 const int64_t q = (int64_t)o + (j - b);
                 if (q < nnz) ci2[q] = u2;
                 if ((unsigned)u2 < (unsigned)n) atomicOr((unsigned long long *)&row[u2 >> 6], 1ull << (u2 & 63));
@@ -1037,6 +1060,7 @@ struct IDesc {
     int32_t *flag;      // [1] previous order not a permutation
     uint32_t *key;      // [1] smallest failing position of the third order
     lexbfs_interval_result_t *res;
+    int32_t ik;         // K of the renamed graph's interleaved tie order, 0 = ids in rank order
 };
 
 constexpr int kIbThreads = 256;
@@ -1063,10 +1087,11 @@ __global__ __launch_bounds__(kIbThreads) void k_ib_rename(const IDesc *__restric
     __syncthreads();
     const bool bad = s_bad != 0;
     if (t == 0) *d.flag = bad ? 1 : 0;
+    const IlvMap map(n, d.ik);
     for (int a = t; a < n; a += kIbThreads) {
         int deg = 0;
         if (!bad) {
-            const int v = prev[n - 1 - a];
+            const int v = prev[n - 1 - (int)map.rank_of((uint32_t)a)];
             deg = d.rp[v + 1] - d.rp[v];
         }
         d.rp2[a + 1] = deg;
@@ -1095,7 +1120,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_ib_rows(const IDesc *__restri
     const int wave = threadIdx.x >> 6;
     rename_rows(d.n, d.nnz, sel == 2 ? d.s2 : d.s1, d.pos, d.rp, d.ci, d.rp2, d.ci2, d.bits2, d.wn, *d.flag != 0,
                 lds + (int64_t)wave * bufw, blockIdx.y * (kBuildThreads / kWave) + wave,
-                gridDim.y * (kBuildThreads / kWave));
+                gridDim.y * (kBuildThreads / kWave), d.ik);
 }
 
 // The renamed pass's order in old ids: s2 from s1 (sel 2) or s3 and its
@@ -1112,6 +1137,7 @@ __global__ __launch_bounds__(kIbThreads) void k_ib_map(const IDesc *__restrict__
     int32_t *rank = sel == 3 ? d.rank3 : nullptr;
     const int32_t *order2 = renamed[blockIdx.x].order;
     const bool bad = *d.flag != 0;
+    const IlvMap map(n, d.ik);
     for (int i = threadIdx.x; i < n; i += kIbThreads) {
         const int a = order2[i];
         if (bad || (unsigned)a >= (unsigned)n) {
@@ -1119,7 +1145,7 @@ __global__ __launch_bounds__(kIbThreads) void k_ib_map(const IDesc *__restrict__
             if (rank) rank[i] = -1;
             continue;
         }
-        const int v = prev[n - 1 - a];
+        const int v = prev[n - 1 - (int)map.rank_of((uint32_t)a)];
         out[i] = v;
         if (rank) rank[v] = i;
     }
@@ -1397,6 +1423,7 @@ GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *o
     d.failkey = (uint32_t *)(ws + L.failkey);
     d.gtab = (uint32_t *)(ws + L.gtab);
     d.res = res;
+    d.ilv = 0;
     return d;
 }
 
@@ -1573,6 +1600,7 @@ struct lexbfs_batch_plan {
     int nbig = 0;    // graphs on 256-lane workgroup teams
     int nsmall = 0;  // graphs on wavefront teams
     int nlarge = 0;  // graphs on 1024-lane workgroups (side stream)
+    std::vector<int32_t> ilv_k;  // per graph: K of its team when its ties use the interleaved order, else 0
     size_t lds = 0;
     size_t lds_large = 0;
     int region = 0;
@@ -1704,9 +1732,11 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
 }
 
 namespace {
+// interleave: graphs on wavefront and 256-lane teams break ties by the
+// interleaved rank (ilv_rank) instead of the id; plan->ilv_k records their K.
 int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs, lexbfs_result_t *res,
                 const lexbfs_tuning_t *tuning, void *ws, size_t ws_bytes, uint32_t flags, void *stream,
-                bool side_stream, lexbfs_batch_plan_t **plan_out)
+                bool side_stream, lexbfs_batch_plan_t **plan_out, bool interleave = false)
 {
     if (!plan_out) return LEXBFS_EINVAL;
     *plan_out = nullptr;
@@ -1804,6 +1834,7 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         }
         d.failkey = (uint32_t *)(w + L.failkeys) + i;
         d.res = res + i;
+        d.ilv = 0;
         hsorted[i] = i;
     }
     auto tier = [&](int i) { return gs[i].n > tier_max ? 2 : gs[i].n > wave_max_n ? 0 : 1; };
@@ -1817,6 +1848,17 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         nbig += t == 0;
         nsmall += t == 1;
     }
+    P->ilv_k.assign(count, 0);
+    if (interleave)
+        for (int i = 0; i < count; ++i) {
+            const int t = tier(i);
+            if (t == 2 || gs[i].n == 0) continue;
+            const int T = t == 0 ? BT : kWave;
+            int K = 1;
+            while (K * T < gs[i].n) K <<= 1;  // the team's vertices per lane, as lexbfs_team computes it
+            hd[i].ilv = 1;
+            P->ilv_k[i] = K;
+        }
     P->nbig = nbig;
     P->nsmall = nsmall;
     P->nlarge = count - nbig - nsmall;
@@ -1940,10 +1982,15 @@ int ui_batch_run(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result
     PlanPair pp;
     int rc = plan_create(gs, count, oa.data(), pres, nullptr, w + U.planA, U.plan.total, 0, s, false, &pp.a);
     if (rc) return rc;
-    rc = plan_create(g2.data(), count, nullptr, pres, nullptr, w + U.planB, U.plan.total, 0, s, false, &pp.b);
+    // The renamed graphs' ties go to the interleaved rank: the renaming below
+    // gives rank order to the previous order reversed, and consecutive ranks
+    // land on different lanes (ids in that order would put a pivot's
+    // neighbours, which are close in it, on one lane).
+    rc = plan_create(g2.data(), count, nullptr, pres, nullptr, w + U.planB, U.plan.total, 0, s, false, &pp.b, true);
     if (rc) return rc;
     pp.a->flags |= kFlagOrderOnly;
     pp.b->flags |= kFlagOrderOnly;
+    for (int i = 0; i < count; ++i) hd[i].ik = pp.b->ilv_k[i];
     const IDesc *dd = (const IDesc *)(w + U.idesc);
     const hipError_t e = hipMemcpyAsync(w + U.idesc, hd.data(), sizeof(IDesc) * (size_t)count, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_hip(e, "staging the interval descriptors");

@@ -568,6 +568,45 @@ __device__ __forceinline__ uint32_t pick_key(uint64_t top, uint64_t nb, uint32_t
     return 0u;
 }
 
+// Interleaved tie-break order. Lane t of a team owns ids t*K + j (slot j,
+// 0 <= j < K; the last owner, lane tl = (n-1)/K, holds the cl = n - tl*K
+// lowest slots). Ranks are dealt slot by slot across the owners: slot 0 of
+// lanes 0..tl, then slot 1, ... -- rank(t, j) = j*tl + min(j, cl) + t. The
+// smallest rank wins a tie instead of the smallest id. Within one lane the
+// rank grows with the slot, as the id does, so a lane's best candidate is
+// still its lowest set bit. A caller that names vertices by rank (a graph
+// renamed so that rank order is the wanted tie order) gets consecutive ranks
+// on different lanes: neighbours of a pivot then spread over the team
+// instead of queueing on one lane.
+__device__ __forceinline__ uint32_t ilv_rank(uint32_t j, uint32_t t, uint32_t tl, uint32_t cl)
+{
+    return j * tl + min(j, cl) + t;
+}
+
+__host__ __device__ __forceinline__ uint32_t ilv_id(uint32_t r, uint32_t tl, uint32_t cl, uint32_t K)
+{
+    const uint32_t A = tl + 1;  // owners of each slot below cl
+    uint32_t j, t;
+    if (r < cl * A) {
+        j = r / A;
+        t = r - j * A;
+    } else {  // tl >= 1 here: slots cl.. have tl owners
+        const uint32_t r2 = r - cl * A;
+        j = cl + r2 / tl;
+        t = r2 - (j - cl) * tl;
+    }
+    return t * K + j;
+}
+
+__device__ __forceinline__ uint32_t pick_key_ilv(uint64_t top, uint64_t nb, int sh, uint32_t t, uint32_t tl,
+                                                 uint32_t cl)
+{
+    const uint64_t a = top & nb;
+    if (a) return 0x20000u | (0xFFFFu - ilv_rank((uint32_t)(ctz64(a) - sh), t, tl, cl));
+    if (top) return 0x10000u | (0xFFFFu - ilv_rank((uint32_t)(ctz64(top) - sh), t, tl, cl));
+    return 0u;
+}
+
 
 // ---------------------------------------------------------------------------
 // LexBFS on one graph by one team.
@@ -585,7 +624,8 @@ __device__ __forceinline__ uint32_t pick_key(uint64_t top, uint64_t nb, uint32_t
 template <class Team, class Tabs, bool kPeo = false>
 __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
                             int32_t *order_, int32_t *rank_, int32_t *parent_, uint64_t *starts, uint16_t *cls,
-                            uint16_t *rem, const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{})
+                            uint16_t *rem, const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{},
+                            bool ilv = false)
 {
     LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
     LX_GLOBAL const int32_t *__restrict__ row_ptr = as_global(row_ptr_);
@@ -605,6 +645,8 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     const int wn = (n + 63) >> 6;
     int K = 1;
     while (K * T < n) K <<= 1;
+    const uint32_t tl = (uint32_t)((n - 1) / K);      // last lane owning vertices (interleaved order)
+    const uint32_t cl = (uint32_t)n - tl * (uint32_t)K; // its number of vertices
     const int vbase = t * K;
     const int wi = vbase >> 6;
     const int sh = vbase & 63;
@@ -745,14 +787,15 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         // in one word -- the candidate class's neighbour count and x's
         // unnumbered-neighbour count (each at most n - 1 < 2^16).
         uint32_t sums = (uint32_t)__popcll(top & nb) | ((uint32_t)__popcll(nb) << 16);
-        const uint32_t k = tm.max_sum_all(pick_key(top, nb, wbase), sums, red + par * 2 * NW);
+        const uint32_t key = ilv ? pick_key_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key(top, nb, wbase);
+        const uint32_t k = tm.max_sum_all(key, sums, red + par * 2 * NW);
         par ^= 1;
         const uint32_t c_adj = sums & 0xFFFFu;
         if (!kPeo) {
             eu -= sums >> 16;
             tail = eu == 0u;
         }
-        const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
+        const uint32_t xn = ilv ? ilv_id(0xFFFFu - (k & 0xFFFFu), tl, cl, (uint32_t)K) : 0xFFFFu - (k & 0xFFFFu);
         const bool adj = (k >> 16) == 2;
         if (adj) top &= nb;  // narrowed to the pivot's neighbours
         // The candidate class spans [cand, U - 1]; its c_adj members adjacent
