@@ -112,7 +112,6 @@ struct GDesc {
     uint32_t *failkey; // [1]
     uint32_t *gtab;    // [2n] class tables in global memory (large n), else null
     lexbfs_result_t *res;
-    int32_t ilv;       // 1: ties go to the smallest interleaved rank (ilv_rank), not id
 };
 
 // ---------------------------------------------------------------------------
@@ -401,7 +400,8 @@ __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
         constexpr bool kRem = kMode == kModeLdsRem;
         LdsLayout<kRem> L = carve_lds<kRem>(lds, g.n, T);
         BlockTeam<T, false> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
+        lexbfs_team<BlockTeam<T, false>, LdsTables<kRem>, false, false, 32>(
+            tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
     }
 }
 
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_close(GDesc g, StepTabs s
 // One graph of a batch on one team, start to finish: LexBFS with the fused
 // elimination test, then (for a failing graph) the witness and certificate,
 // reusing the team's LDS region.
-template <class Team, bool kMcs>
+template <class Team, bool kMcs, bool kIlv = false>
 __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32_t flags)
 {
     if (kMcs) {
@@ -564,8 +564,8 @@ __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32
                              carve_mcs(region, g.n, Team::kSize, true, g.failkey));
     } else {
         BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
-        lexbfs_team<Team, LdsTables<true>, true>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, B.L.starts,
-                                                  B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp, g.ilv != 0);
+        lexbfs_team<Team, LdsTables<true>, true, kIlv>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent,
+                                                        B.L.starts, B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
     }
     tm.sync_mem();  // order, rank, parent and the failing rank visible to the team
     if (!(flags & kFlagOrderOnly)) finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bitset(int n, const int
 
 // Batch: every block first takes large graphs (whole block per graph) from a
 // longest-first queue; once those run out every wave takes small graphs.
-template <int BT, bool kMcs>
+template <int BT, bool kMcs, bool kIlv = false>
 __global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, const int32_t *__restrict__ sorted,
                                               int nbig, int count, uint32_t *qctr, int wave_region_bytes,
                                               uint32_t flags)
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, con
         __syncthreads();
         if (k >= nbig) break;
         BlockTeam<BT, false> tm{(int)threadIdx.x};
-        batch_graph<BlockTeam<BT, false>, kMcs>(tm, gds[sorted[k]], lds, flags);
+        batch_graph<BlockTeam<BT, false>, kMcs, kIlv>(tm, gds[sorted[k]], lds, flags);
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     void *region = (char *)lds + (size_t)wave * wave_region_bytes;
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(BT) void k_batch(const GDesc *__restrict__ gds, con
         k = __shfl(k, 0, kWave);
         if (k >= nsmall) break;
         WaveTeam tm{lane};
-        batch_graph<WaveTeam, kMcs>(tm, gds[sorted[nbig + k]], region, flags);
+        batch_graph<WaveTeam, kMcs, kIlv>(tm, gds[sorted[nbig + k]], region, flags);
     }
 }
 
@@ -1250,6 +1250,7 @@ int single_threads(int n)
     if (forced == 64 || forced == 128 || forced == 256 || forced == 512 || forced == 1024) T = forced;
     else if (n <= 1024) T = 64;
     else if (n <= 4096) T = 256;
+    else if (n <= 32768) T = 512;  // measured: 1.3-2.0 us/step against 1.75-2.2 on 1024 lanes
     else T = 1024;
     while ((int64_t)T * 64 < n) T <<= 1;
     return T;
@@ -1423,7 +1424,6 @@ GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *o
     d.failkey = (uint32_t *)(ws + L.failkey);
     d.gtab = (uint32_t *)(ws + L.gtab);
     d.res = res;
-    d.ilv = 0;
     return d;
 }
 
@@ -1601,6 +1601,7 @@ struct lexbfs_batch_plan {
     int nsmall = 0;  // graphs on wavefront teams
     int nlarge = 0;  // graphs on 1024-lane workgroups (side stream)
     std::vector<int32_t> ilv_k;  // per graph: K of its team when its ties use the interleaved order, else 0
+    bool interleaved = false;    // launch the interleaved-tie batch kernel
     size_t lds = 0;
     size_t lds_large = 0;
     int region = 0;
@@ -1834,7 +1835,6 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         }
         d.failkey = (uint32_t *)(w + L.failkeys) + i;
         d.res = res + i;
-        d.ilv = 0;
         hsorted[i] = i;
     }
     auto tier = [&](int i) { return gs[i].n > tier_max ? 2 : gs[i].n > wave_max_n ? 0 : 1; };
@@ -1849,6 +1849,7 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         nsmall += t == 1;
     }
     P->ilv_k.assign(count, 0);
+    P->interleaved = interleave;
     if (interleave)
         for (int i = 0; i < count; ++i) {
             const int t = tier(i);
@@ -1856,7 +1857,6 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
             const int T = t == 0 ? BT : kWave;
             int K = 1;
             while (K * T < gs[i].n) K <<= 1;  // the team's vertices per lane, as lexbfs_team computes it
-            hd[i].ilv = 1;
             P->ilv_k[i] = K;
         }
     P->nbig = nbig;
@@ -1991,6 +1991,9 @@ int ui_batch_run(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result
     pp.a->flags |= kFlagOrderOnly;
     pp.b->flags |= kFlagOrderOnly;
     for (int i = 0; i < count; ++i) hd[i].ik = pp.b->ilv_k[i];
+    // The interleaved-tie batch kernel has the same LDS layout; raise its limit.
+    if (dynamic_lds_limit(k_batch<kBatchThreads, false, true>) < pp.b->lds)
+        return fail_code(LEXBFS_EHIP, "raising the interleaved batch kernel's LDS limit failed");
     const IDesc *dd = (const IDesc *)(w + U.idesc);
     const hipError_t e = hipMemcpyAsync(w + U.idesc, hd.data(), sizeof(IDesc) * (size_t)count, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_hip(e, "staging the interval descriptors");
@@ -2081,6 +2084,9 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
         if (P->flags & LEXBFS_FLAG_MCS)
             hipLaunchKernelGGL((k_batch<BT, true>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted, P->nbig,
                                P->nbig + P->nsmall, qctr, P->region, P->flags);
+        else if (P->interleaved)
+            hipLaunchKernelGGL((k_batch<BT, false, true>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted,
+                               P->nbig, P->nbig + P->nsmall, qctr, P->region, P->flags);
         else
             hipLaunchKernelGGL((k_batch<BT, false>), dim3(P->blocks), dim3(BT), P->lds, s, dg, sorted, P->nbig,
                                P->nbig + P->nsmall, qctr, P->region, P->flags);

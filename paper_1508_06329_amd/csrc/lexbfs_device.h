@@ -621,11 +621,13 @@ __device__ __forceinline__ uint32_t pick_key_ilv(uint64_t top, uint64_t nb, int 
 // v is chosen) and keeps the smallest failing rank; parents are collected in
 // LDS and written out at the end. Needs n < 65536 (16-bit parents).
 // ---------------------------------------------------------------------------
-template <class Team, class Tabs, bool kPeo = false>
+// kIlv: ties go to the smallest interleaved rank (ilv_rank) instead of the
+// smallest id. kPre: the largest K whose class ids the gone case loads
+// early (8, 16 or 32; wider K matches from LDS), a register budget.
+template <class Team, class Tabs, bool kPeo = false, bool kIlv = false, int kPre = 16>
 __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
                             int32_t *order_, int32_t *rank_, int32_t *parent_, uint64_t *starts, uint16_t *cls,
-                            uint16_t *rem, const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{},
-                            bool ilv = false)
+                            uint16_t *rem, const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{})
 {
     LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
     LX_GLOBAL const int32_t *__restrict__ row_ptr = as_global(row_ptr_);
@@ -694,19 +696,23 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         const bool gone = (int)stop == U;  // x was the last member of the top class
         // What the gone case reads, loaded now, in the shadow of the pivot
         // row: the two class-start words at and below position U - 1 and the
-        // class ids of my chunk (K = 8 or 16). Nothing changes them before the
-        // case uses them: phase A writes neither, and the class start cleared
-        // below is U, above U - 1.
+        // class ids of my chunk (K = 8, 16 or 32: one 16-byte read per 8 ids).
+        // Nothing changes them before the case uses them: phase A writes
+        // neither, and the class start cleared below is U, above U - 1.
+        constexpr int kQ = kPre / 8;
         uint64_t s_hi = 0ull, s_lo = 0ull;
-        uint4 c_lo = make_uint4(0u, 0u, 0u, 0u), c_hi = make_uint4(0u, 0u, 0u, 0u);
+        uint4 cc[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) cc[q] = make_uint4(0u, 0u, 0u, 0u);
         if (gone && U > 0) {
             const int pw = (U - 1) >> 6;
             s_hi = starts[pw];
             if (pw > 0) s_lo = starts[pw - 1];
-            if ((K == 8 || K == 16) && owner) {
+            if (K >= 8 && K <= kPre && owner) {
                 const uint4 *p = (const uint4 *)(cls + vbase);
-                c_lo = p[0];
-                if (K == 16 && vbase + 8 < n) c_hi = p[1];
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    if (8 * q < K && vbase + 8 * q < n) cc[q] = p[q];  // only ids below n
             }
         }
         if (owner && (x >> 6) == (uint32_t)wi) {
@@ -779,15 +785,21 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
                 cand = tm.max_all(hi, red + par * 2 * NW) - 1u;
                 par ^= 1;
             }
-            if (K == 16) top = ((uint64_t)(match8(c_lo, cand) | match8(c_hi, cand) << 8) << sh) & um;
-            else if (K == 8) top = ((uint64_t)match8(c_lo, cand) << sh) & um;
-            else top = chunk_match(cls, um, cand, vbase, sh, K);
+            if (K >= 8 && K <= kPre) {
+                uint64_t mm = 0ull;
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    if (8 * q < K) mm |= (uint64_t)match8(cc[q], cand) << (8 * q);
+                top = (mm << sh) & um;
+            } else {
+                top = chunk_match(cls, um, cand, vbase, sh, K);
+            }
         }
         // One reduction: the selection key (max) and two 16-bit sums packed
         // in one word -- the candidate class's neighbour count and x's
         // unnumbered-neighbour count (each at most n - 1 < 2^16).
         uint32_t sums = (uint32_t)__popcll(top & nb) | ((uint32_t)__popcll(nb) << 16);
-        const uint32_t key = ilv ? pick_key_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key(top, nb, wbase);
+        const uint32_t key = kIlv ? pick_key_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key(top, nb, wbase);
         const uint32_t k = tm.max_sum_all(key, sums, red + par * 2 * NW);
         par ^= 1;
         const uint32_t c_adj = sums & 0xFFFFu;
@@ -795,7 +807,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             eu -= sums >> 16;
             tail = eu == 0u;
         }
-        const uint32_t xn = ilv ? ilv_id(0xFFFFu - (k & 0xFFFFu), tl, cl, (uint32_t)K) : 0xFFFFu - (k & 0xFFFFu);
+        const uint32_t xn = kIlv ? ilv_id(0xFFFFu - (k & 0xFFFFu), tl, cl, (uint32_t)K) : 0xFFFFu - (k & 0xFFFFu);
         const bool adj = (k >> 16) == 2;
         if (adj) top &= nb;  // narrowed to the pivot's neighbours
         // The candidate class spans [cand, U - 1]; its c_adj members adjacent
@@ -992,6 +1004,27 @@ __device__ __forceinline__ uint32_t next_start(const uint64_t *starts, const uin
     return U;
 }
 
+// The highest class start at or below position pos (position 0 always
+// starts a class). Words above pos >> 6 are never consulted in the summary,
+// so a concurrent clear of a start above pos does not disturb the lookup.
+__device__ __forceinline__ uint32_t prev_start(const uint64_t *starts, const uint64_t *sum, uint32_t pos)
+{
+    const uint32_t w = pos >> 6;
+    const uint64_t m = starts[w] & (~0ull >> (63u - (pos & 63u)));
+    if (m) return (w << 6) | (uint32_t)(63 - __builtin_clzll(m));
+    if (w == 0) return 0;
+    const uint32_t w1 = w - 1u;
+    for (int s1 = (int)(w1 >> 6); s1 >= 0; --s1) {
+        uint64_t mm = sum[s1];
+        if (s1 == (int)(w1 >> 6)) mm &= ~0ull >> (63u - (w1 & 63u));
+        if (mm) {
+            const uint32_t ww = ((uint32_t)s1 << 6) | (uint32_t)(63 - __builtin_clzll(mm));
+            return (ww << 6) | (uint32_t)(63 - __builtin_clzll(starts[ww]));
+        }
+    }
+    return 0;
+}
+
 template <class Team>
 __device__ void lexbfs_team_compact(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_,
                                     int32_t *rank_, int32_t *parent_, const CompactLayout &L)
@@ -1068,20 +1101,14 @@ __device__ void lexbfs_team_compact(const Team &tm, int n, const uint64_t *bits_
             if (cnt_inc(C) == 0) lead |= 1ull << b;
         }
         if (i + 1 == n) break;
-        uint32_t k = tm.max_all(pick_key(top, nb, wbase), red + par * 2 * NW);
-        par ^= 1;
-        if ((k >> 16) == 0) {
-            uint32_t hi = 0;
-            for (int w = t; w < wn; w += T) {
-                const uint64_t sw = starts[w];
-                if (sw) hi = max(hi, (uint32_t)((w << 6) | (63 - __builtin_clzll(sw))) + 1u);
-            }
-            const uint32_t c1 = tm.max_all(hi, red + par * 2 * NW) - 1u;
-            par ^= 1;
-            top = chunk_match(cls, um, c1, vbase, sh, K);
-            k = tm.max_all(pick_key(top, nb, wbase), red + par * 2 * NW);
-            par ^= 1;
+        if ((int)stop >= U) {
+            // x emptied the top class: the candidate is the class holding
+            // position U - 1, found by every lane alike from the class-start
+            // bitmap and its summary (no team scan and no extra reduction).
+            top = chunk_match(cls, um, prev_start(starts, sum, (uint32_t)(U - 1)), vbase, sh, K);
         }
+        const uint32_t k = tm.max_all(pick_key(top, nb, wbase), red + par * 2 * NW);
+        par ^= 1;
         const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
         if ((k >> 16) == 2) top &= nb;
         const uint64_t rwn = owner ? rowbase[(int64_t)xn * W] : 0ull;
