@@ -1248,7 +1248,8 @@ int single_threads(int n)
     }
     int T;
     if (forced == 64 || forced == 128 || forced == 256 || forced == 512 || forced == 1024) T = forced;
-    else if (n <= 1024) T = 64;
+    else if (n <= 512) T = 64;
+    else if (n <= 1024) T = 128;   // measured: 3-4% fewer cycles per step than one wavefront
     else if (n <= 4096) T = 256;
     else if (n <= 32768) T = 512;  // measured: 1.3-2.0 us/step against 1.75-2.2 on 1024 lanes
     else T = 1024;
