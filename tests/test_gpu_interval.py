@@ -91,6 +91,15 @@ def test_full_size():
     check_plus(g, gg.permutation(g.n, 6), tag="N=65536 gnp")
 
 
+def test_compact_layout_sizes():
+    """n = 20,000-32,768: the compact LDS form of the LexBFS kernel (class
+    ends from the class-start bitmap) in every sweep."""
+    check_interval(gg.intervals(25000, 10, 31), tag="N=25000 unit")
+    check_interval(gg.intervals(32768, 10, 32, unit=False), tag="N=32768 mixed")
+    g = gg.gnp(20000, 0.0005, 33)
+    check_plus(g, gg.permutation(g.n, 34), tag="N=20000 gnp")
+
+
 def test_prev_not_a_permutation():
     """The device detects a prev_order that is not a permutation and fills
     the outputs with -1."""
