@@ -383,7 +383,9 @@ __device__ void finish_graph(const Team &tm, const GDesc &g, uint32_t flags, con
 // State placement of a single-graph LexBFS launch, most capable first.
 enum : int { kModeLdsRem = 0, kModeLds = 1, kModeCompact = 2, kModeGlobal = 3 };
 
-template <int T, int kMode>
+// kIlv: ties by the interleaved rank (the renamed graphs of LexBFS+ sweeps);
+// never used with the compact form.
+template <int T, int kMode, bool kIlv = false>
 __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
 {
     extern __shared__ uint64_t lds[];
@@ -395,12 +397,13 @@ __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
         LdsLayoutG L = carve_lds_g(lds, g.n, T);
         GlobalTables tab{g.gtab, g.gtab + g.n};
         BlockTeam<T, true> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, nullptr, tab, L.red);
+        lexbfs_team<BlockTeam<T, true>, GlobalTables, false, kIlv>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank,
+                                                                  g.parent, L.starts, L.cls, nullptr, tab, L.red);
     } else {
         constexpr bool kRem = kMode == kModeLdsRem;
         LdsLayout<kRem> L = carve_lds<kRem>(lds, g.n, T);
         BlockTeam<T, false> tm{(int)threadIdx.x};
-        lexbfs_team<BlockTeam<T, false>, LdsTables<kRem>, false, false, 32>(
+        lexbfs_team<BlockTeam<T, false>, LdsTables<kRem>, false, kIlv, 32>(
             tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
     }
 }
@@ -722,6 +725,26 @@ constexpr int kPlusThreads = 256;
 constexpr int kPlusScanThreads = 1024;
 constexpr int kPlusPerLane = LEXBFS_MAX_N / kPlusScanThreads;  // rows summed by one lane of the scan
 
+// New ids of a renamed graph against tie ranks (the previous order
+// reversed): equal when K = 0, else the interleaved order of a team with K
+// vertices per lane (ilv_rank / ilv_id).
+struct IlvMap {
+    uint32_t K, lgK, tl, cl;
+    __device__ IlvMap(int n, int k) : K((uint32_t)k), lgK(0), tl(0), cl(0)
+    {
+        if (K) {
+            while ((1u << lgK) < K) ++lgK;
+            tl = (uint32_t)(n - 1) >> lgK;
+            cl = (uint32_t)n - (tl << lgK);
+        }
+    }
+    __device__ __forceinline__ uint32_t rank_of(uint32_t a) const
+    {
+        return K ? ilv_rank(a & (K - 1), a >> lgK, tl, cl) : a;
+    }
+    __device__ __forceinline__ uint32_t id_of(uint32_t r) const { return K ? ilv_id(r, tl, cl, K) : r; }
+};
+
 // pos[v] = -1 for every v, flag = 0, and (when given) the interval key to
 // "no failure".
 __global__ __launch_bounds__(kPlusThreads) void k_plus_init(int n, int32_t *pos, int32_t *flag, uint32_t *key)
@@ -750,13 +773,14 @@ __global__ __launch_bounds__(kPlusThreads) void k_plus_inverse(int n, const int3
 // turns the renamed graph into an edgeless one.
 __global__ __launch_bounds__(kPlusThreads) void k_plus_degree(int n, int npad, const int32_t *__restrict__ prev,
                                                               const int32_t *__restrict__ rp,
-                                                              const int32_t *__restrict__ flag, int32_t *deg)
+                                                              const int32_t *__restrict__ flag, int32_t *deg, int ik)
 {
     const int a = blockIdx.x * kPlusThreads + threadIdx.x;
     if (a >= npad) return;
     int d = 0;
     if (a < n && *flag == 0) {
-        const int v = prev[n - 1 - a];
+        const IlvMap map(n, ik);
+        const int v = prev[n - 1 - (int)map.rank_of((uint32_t)a)];
         d = rp[v + 1] - rp[v];
     }
     deg[a] = d;
@@ -794,26 +818,6 @@ __global__ __launch_bounds__(kPlusScanThreads) void k_plus_scan(int n, const int
         }
     }
 }
-
-// New ids of a renamed graph against tie ranks (the previous order
-// reversed): equal when K = 0, else the interleaved order of a team with K
-// vertices per lane (ilv_rank / ilv_id).
-struct IlvMap {
-    uint32_t K, lgK, tl, cl;
-    __device__ IlvMap(int n, int k) : K((uint32_t)k), lgK(0), tl(0), cl(0)
-    {
-        if (K) {
-            while ((1u << lgK) < K) ++lgK;
-            tl = (uint32_t)(n - 1) >> lgK;
-            cl = (uint32_t)n - (tl << lgK);
-        }
-    }
-    __device__ __forceinline__ uint32_t rank_of(uint32_t a) const
-    {
-        return K ? ilv_rank(a & (K - 1), a >> lgK, tl, cl) : a;
-    }
-    __device__ __forceinline__ uint32_t id_of(uint32_t r) const { return K ? ilv_id(r, tl, cl, K) : r; }
-};
 
 // Lanes per renamed row (log2): rows of up to 64 words get the smallest
 // power of two >= W2, at most 16, so a wavefront works on at least four
@@ -888,14 +892,14 @@ __global__ __launch_bounds__(kPlusThreads) void k_plus_rows(int n, int64_t nnz, 
                                                             const int32_t *__restrict__ ci,
                                                             const int32_t *__restrict__ flag,
                                                             const int32_t *__restrict__ rp2, int32_t *ci2,
-                                                            uint64_t *bits2)
+                                                            uint64_t *bits2, int ik)
 {
     extern __shared__ uint64_t lds[];
     const int W2 = (n + 63) / 64;
     const int wave = threadIdx.x >> 6;
     rename_rows(n, nnz, prev, pos, rp, ci, rp2, ci2, bits2, W2, *flag != 0,
                 lds + (int64_t)wave * rename_buffer_words(W2), blockIdx.x * (kPlusThreads / kWave) + wave,
-                gridDim.x * (kPlusThreads / kWave));
+                gridDim.x * (kPlusThreads / kWave), ik);
 }
 
 // The renamed sweep's outputs in old ids: order[i] = prev[n-1-order2[i]],
@@ -905,7 +909,7 @@ __global__ __launch_bounds__(kPlusThreads) void k_plus_map(int n, const int32_t 
                                                            const int32_t *__restrict__ order2,
                                                            const int32_t *__restrict__ parent2,
                                                            const int32_t *__restrict__ flag, int32_t *order,
-                                                           int32_t *rank, int32_t *parent)
+                                                           int32_t *rank, int32_t *parent, int ik)
 {
     const int i = blockIdx.x * kPlusThreads + threadIdx.x;
     if (i >= n) return;
@@ -916,12 +920,13 @@ __global__ __launch_bounds__(kPlusThreads) void k_plus_map(int n, const int32_t 
         if (parent) parent[i] = -1;
         return;
     }
-    const int v = prev[n - 1 - a];
+    const IlvMap map(n, ik);
+    const int v = prev[n - 1 - (int)map.rank_of((uint32_t)a)];
     order[i] = v;
     if (rank) rank[v] = i;
     if (parent) {
         const int p = parent2[a];
-        parent[v] = (unsigned)p < (unsigned)n ? prev[n - 1 - p] : -1;
+        parent[v] = (unsigned)p < (unsigned)n ? prev[n - 1 - (int)map.rank_of((uint32_t)p)] : -1;
     }
 }
 
@@ -1292,8 +1297,11 @@ SingleWs single_layout(int n)
     return L;
 }
 
+// The LDS form the single-graph LexBFS kernel takes for n vertices on a
+// T-lane team: the first of tables with rem, tables, compact, global tables
+// that fits.
 template <int T>
-int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
+int single_mode_T(int n, int &mode)
 {
     const size_t lim_r = dynamic_lds_limit(k_lexbfs_single<T, kModeLdsRem>);
     const size_t lim_l = dynamic_lds_limit(k_lexbfs_single<T, kModeLds>);
@@ -1301,36 +1309,84 @@ int launch_lexbfs_single_T(const GDesc &d, hipStream_t s)
     const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, kModeGlobal>);
     if (!lim_r || !lim_l || !lim_c || !lim_g)
         return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
-    const size_t b_r = lds_bytes_lds_tables(d.n, T, true);
-    const size_t b_l = lds_bytes_lds_tables(d.n, T, false);
-    const size_t b_g = lds_bytes_global_tables(d.n, T);
+    if (lds_bytes_lds_tables(n, T, true) <= lim_r) mode = kModeLdsRem;
+    else if (lds_bytes_lds_tables(n, T, false) <= lim_l) mode = kModeLds;
+    else if (lds_bytes_compact(n, T) <= lim_c) mode = kModeCompact;
+    else if (lds_bytes_global_tables(n, T) <= lim_g) mode = kModeGlobal;
+    else return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
+    return LEXBFS_OK;
+}
+
+template <int T, int kMode>
+int launch_single_mode(const GDesc &d, hipStream_t s, bool ilv, size_t lds)
+{
+    if (ilv) {
+        if (dynamic_lds_limit(k_lexbfs_single<T, kMode, true>) < lds)
+            return fail_code(LEXBFS_EHIP, "raising the LexBFS kernel's LDS limit failed");
+        hipLaunchKernelGGL((k_lexbfs_single<T, kMode, true>), dim3(1), dim3(T), lds, s, d);
+    } else {
+        hipLaunchKernelGGL((k_lexbfs_single<T, kMode>), dim3(1), dim3(T), lds, s, d);
+    }
+    return LEXBFS_OK;
+}
+
+template <int T>
+int launch_lexbfs_single_T(const GDesc &d, hipStream_t s, bool ilv)
+{
+    int mode = 0;
+    int rc = single_mode_T<T>(d.n, mode);
+    if (rc) return rc;
     ProfScope ps(0, s);
-    if (b_r <= lim_r) {
-        hipLaunchKernelGGL((k_lexbfs_single<T, kModeLdsRem>), dim3(1), dim3(T), b_r, s, d);
-    } else if (b_l <= lim_l) {
-        hipLaunchKernelGGL((k_lexbfs_single<T, kModeLds>), dim3(1), dim3(T), b_l, s, d);
-    } else if (lds_bytes_compact(d.n, T) <= lim_c) {
+    if (mode == kModeLdsRem) {
+        rc = launch_single_mode<T, kModeLdsRem>(d, s, ilv, lds_bytes_lds_tables(d.n, T, true));
+    } else if (mode == kModeLds) {
+        rc = launch_single_mode<T, kModeLds>(d, s, ilv, lds_bytes_lds_tables(d.n, T, false));
+    } else if (mode == kModeCompact) {
         hipLaunchKernelGGL((k_lexbfs_single<T, kModeCompact>), dim3(1), dim3(T), lds_bytes_compact(d.n, T), s, d);
     } else {
-        if (b_g > lim_g) return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
-        hipLaunchKernelGGL((k_lexbfs_single<T, kModeGlobal>), dim3(1), dim3(T), b_g, s, d);
+        rc = launch_single_mode<T, kModeGlobal>(d, s, ilv, lds_bytes_global_tables(d.n, T));
+        if (rc) return rc;
         LX_CHECK_LAUNCH("LexBFS launch");
         const int blocks = std::min((d.n + 3) / 4, 2048);
         hipLaunchKernelGGL(k_parents, dim3(blocks), dim3(256), 0, s, d);
     }
+    if (rc) return rc;
     LX_CHECK_LAUNCH("LexBFS launch");
     return LEXBFS_OK;
 }
 
-int launch_lexbfs_single(const GDesc &d, hipStream_t s)
+// ilv: ties by the interleaved rank; only for the forms other than compact
+// (single_ilv_k says which).
+int launch_lexbfs_single(const GDesc &d, hipStream_t s, bool ilv = false)
 {
     switch (single_threads(d.n)) {
-        case 64: return launch_lexbfs_single_T<64>(d, s);
-        case 128: return launch_lexbfs_single_T<128>(d, s);
-        case 256: return launch_lexbfs_single_T<256>(d, s);
-        case 512: return launch_lexbfs_single_T<512>(d, s);
-        default: return launch_lexbfs_single_T<1024>(d, s);
+        case 64: return launch_lexbfs_single_T<64>(d, s, ilv);
+        case 128: return launch_lexbfs_single_T<128>(d, s, ilv);
+        case 256: return launch_lexbfs_single_T<256>(d, s, ilv);
+        case 512: return launch_lexbfs_single_T<512>(d, s, ilv);
+        default: return launch_lexbfs_single_T<1024>(d, s, ilv);
     }
+}
+
+// K of the interleaved tie order the single-graph kernel uses for n
+// vertices, or 0 when its form (compact) keeps ids in rank order; < 0 on a
+// failure.
+int single_ilv_k(int n)
+{
+    const int T = single_threads(n);
+    int mode = 0, rc = 0;
+    switch (T) {
+        case 64: rc = single_mode_T<64>(n, mode); break;
+        case 128: rc = single_mode_T<128>(n, mode); break;
+        case 256: rc = single_mode_T<256>(n, mode); break;
+        case 512: rc = single_mode_T<512>(n, mode); break;
+        default: rc = single_mode_T<1024>(n, mode); break;
+    }
+    if (rc) return rc;
+    if (mode == kModeCompact) return 0;
+    int K = 1;
+    while (K * T < n) K <<= 1;
+    return K;
 }
 
 template <int T>
@@ -1554,18 +1610,23 @@ int plus_sweep(const lexbfs_graph_t *g, const int32_t *prev, int32_t *order, int
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
+    // The renamed graph's ids follow the kernel's interleaved tie order where
+    // its LDS form supports one, so that a pivot's neighbours (close together
+    // in the previous order) do not all land on one lane.
+    const int ik = single_ilv_k(n);
+    if (ik < 0) return ik;
     {
         ProfScope ps(3, s);
         hipLaunchKernelGGL(k_plus_init, dim3(blocks), dim3(kPlusThreads), 0, s, n, pos, flag, key);
         hipLaunchKernelGGL(k_plus_inverse, dim3(blocks), dim3(kPlusThreads), 0, s, n, prev, pos, flag);
         hipLaunchKernelGGL(k_plus_degree, dim3((npad + kPlusThreads - 1) / kPlusThreads), dim3(kPlusThreads), 0, s,
-                           n, npad, prev, g->row_ptr, (const int32_t *)flag, deg);
+                           n, npad, prev, g->row_ptr, (const int32_t *)flag, deg, ik);
         hipLaunchKernelGGL(k_plus_scan, dim3(1), dim3(kPlusScanThreads), 0, s, n, (const int32_t *)deg, rp2);
         const int rblocks = std::max(1, std::min((n + 3) / 4, cus * 8));
         const size_t rlds = (size_t)(kPlusThreads / kWave) * 8 * (size_t)rename_buffer_words((n + 63) / 64);
         hipLaunchKernelGGL(k_plus_rows, dim3(rblocks), dim3(kPlusThreads), rlds, s, n, g->nnz, prev,
                            (const int32_t *)pos, g->row_ptr, g->col_idx, (const int32_t *)flag, (const int32_t *)rp2,
-                           ci2, bits2);
+                           ci2, bits2, ik);
         LX_CHECK_LAUNCH("LexBFS+ renaming launches");
     }
     lexbfs_graph_t g2;
@@ -1577,12 +1638,12 @@ int plus_sweep(const lexbfs_graph_t *g, const int32_t *prev, int32_t *order, int
     g2.bits = bits2;
     g2.words_per_row = (n + 63) / 64;
     const GDesc d = make_desc(&g2, ws + P.lex, single_layout(n), nullptr, nullptr, nullptr, nullptr, nullptr);
-    int rc = launch_lexbfs_single(d, s);
+    int rc = launch_lexbfs_single(d, s, ik > 0);
     if (rc) return rc;
     {
         ProfScope ps(3, s);
         hipLaunchKernelGGL(k_plus_map, dim3(blocks), dim3(kPlusThreads), 0, s, n, prev, (const int32_t *)d.order,
-                           (const int32_t *)d.parent, (const int32_t *)flag, order, rank, parent);
+                           (const int32_t *)d.parent, (const int32_t *)flag, order, rank, parent, ik);
     }
     LX_CHECK_LAUNCH("LexBFS+ order launch");
     return LEXBFS_OK;

@@ -687,7 +687,9 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     // Single graphs: edges with both ends unnumbered. Once none is left, no
     // later pivot has an unnumbered neighbour, so nothing splits any more and
     // the team finishes in the tail loop below.
-    uint32_t eu = kPeo ? 1u : (uint32_t)(row_ptr[n] >> 1);
+    // (Not with interleaved ties: the tail ranks a class's members in id
+    // order.)
+    uint32_t eu = (kPeo || kIlv) ? 1u : (uint32_t)(row_ptr[n] >> 1);
     bool tail = false;
     int i = 0;
     for (; i < n; ++i) {
@@ -803,7 +805,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         const uint32_t k = tm.max_sum_all(key, sums, red + par * 2 * NW);
         par ^= 1;
         const uint32_t c_adj = sums & 0xFFFFu;
-        if (!kPeo) {
+        if (!kPeo && !kIlv) {
             eu -= sums >> 16;
             tail = eu == 0u;
         }
@@ -877,7 +879,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             break;
         }
     }
-    if (!kPeo && tail) {
+    if (!kPeo && !kIlv && tail) {
         // Tail: no unnumbered vertex has an unnumbered neighbour, so nothing
         // splits any more and the remaining steps only walk down the classes,
         // smallest id first within a class. With U0 = n - i unnumbered
