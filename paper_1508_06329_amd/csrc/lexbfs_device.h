@@ -1245,10 +1245,12 @@ __device__ __forceinline__ void sweep_rows(const uint64_t *bits_, int64_t W, int
         const uint64_t bal = __ballot(fail);
         if (bal & gmask) best = min(best, (uint32_t)rv);
     }
-    // One atomic per wavefront: in a graph where most rows fail, one per
-    // failing row would queue thousands of atomics on a single L2 word.
+    // At most one atomic per wavefront, and only when it would lower the
+    // current minimum: in a graph where most rows fail, an atomic per failing
+    // row (or even per wavefront) queues thousands of them on one L2 word.
     best = wave_min_u32(best);
-    if (lane == 0 && best != kNoFail)
+    if (lane == 0 && best != kNoFail &&
+        best < __hip_atomic_load(failkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         __hip_atomic_fetch_min(failkey, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
