@@ -435,11 +435,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep_single(GDesc g, int row
     sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, r0, r1, G, lg, g.failkey);
 }
 
-__global__ __launch_bounds__(kFinishThreads) void k_finish_single(GDesc g, uint32_t flags)
+// Verdict, witness and certificate of one graph on a T-lane workgroup
+// (1,024 lanes for graphs with rows over 64 words: the certificate's BFS
+// scans rows word-parallel).
+template <int T>
+__global__ __launch_bounds__(T) void k_finish_single(GDesc g, uint32_t flags)
 {
     extern __shared__ uint64_t lds[];
-    BlockTeam<kFinishThreads, false> tm{(int)threadIdx.x};
-    finish_graph(tm, g, flags, carve_finish(lds, g.wn, kFinishThreads / kWave));
+    BlockTeam<T, false> tm{(int)threadIdx.x};
+    finish_graph(tm, g, flags, carve_finish(lds, g.wn, T / kWave));
 }
 
 // ---------------------------------------------------------------------------
@@ -1784,7 +1788,12 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
     }
     {
         ProfScope ps(2, s);
-        hipLaunchKernelGGL(k_finish_single, dim3(1), dim3(kFinishThreads), finish_lds(d.wn), s, d, flags);
+        if (d.wn > kWave)
+            hipLaunchKernelGGL(k_finish_single<kLargeThreads>, dim3(1), dim3(kLargeThreads),
+                               finish_lds_bytes(d.wn, kLargeThreads / kWave), s, d, flags);
+        else
+            hipLaunchKernelGGL(k_finish_single<kFinishThreads>, dim3(1), dim3(kFinishThreads), finish_lds(d.wn), s, d,
+                               flags);
     }
     LX_CHECK_LAUNCH("certificate launch");
     return LEXBFS_OK;
