@@ -1120,8 +1120,9 @@ __global__ __launch_bounds__(kIbThreads) void k_ib_rename(const IDesc *__restric
 }
 
 // Renamed CSR rows and bitsets: graph blockIdx.x, rows spread over the
-// gridDim.y workgroups of its grid row; `bufw` LDS words per wavefront
-// (rename_buffer_words of the widest row).
+// gridDim.y workgroups of its grid row; `bufw` LDS words per wavefront, the
+// largest rename_buffer_words over the batch's graphs (not that of the widest
+// row: graphs of up to 64-word rows buffer four rows per wavefront).
 __global__ __launch_bounds__(kBuildThreads) void k_ib_rows(const IDesc *__restrict__ ds, int sel, int bufw)
 {
     extern __shared__ uint64_t lds[];
@@ -2013,7 +2014,7 @@ int ui_batch_run(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result
     std::vector<IDesc> hd(count);
     std::vector<lexbfs_graph_t> g2(count);
     std::vector<lexbfs_outputs_t> oa(count);
-    int maxn = 0, maxw = 1;
+    int maxn = 0, bufw = 1;
     for (int i = 0; i < count; ++i) {
         const lexbfs_graph_t &g = gs[i];
         const size_t m = (size_t)std::max(g.n, 1);
@@ -2049,7 +2050,7 @@ int ui_batch_run(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result
         oa[i].order = d.s1;
         oa[i].rank = oa[i].parent = oa[i].cycle = nullptr;
         maxn = std::max(maxn, g.n);
-        maxw = std::max(maxw, d.wn);
+        bufw = std::max(bufw, rename_buffer_words(std::max(d.wn, 1)));
     }
     lexbfs_result_t *pres = (lexbfs_result_t *)(w + U.pres);
     PlanPair pp;
@@ -2080,7 +2081,6 @@ int ui_batch_run(const lexbfs_graph_t *gs, int32_t count, lexbfs_interval_result
         {
             ProfScope ps(3, s);
             hipLaunchKernelGGL(k_ib_rename, dim3(count), dim3(kIbThreads), 0, s, dd, sel);
-            const int bufw = rename_buffer_words(maxw);
             hipLaunchKernelGGL(k_ib_rows, dim3(count, ybits), dim3(kBuildThreads),
                                (size_t)(kBuildThreads / kWave) * 8 * (size_t)bufw, s, dd, sel, bufw);
         }

@@ -180,3 +180,29 @@ def test_batch_full_workload():
     assert sum(r.unit_interval for r in rs) > 0
     sample = graphs[::64]
     check_batch(sample, "sample with orders")
+
+
+BOUNDARY_SIZES = [63, 64, 65, 127, 129, 511, 512, 513, 1000, 1023, 1024, 1025, 2047, 2049, 4095, 4096, 4097,
+                  8191, 8193]
+
+
+@pytest.mark.parametrize("n", BOUNDARY_SIZES)
+def test_interleaved_order_at_team_boundaries(n):
+    """Sizes around every team-size and chunk boundary: the renamed sweeps
+    deal ranks across lanes with a partial last chunk (cl < K) and n not a
+    multiple of 64."""
+    rng = np.random.default_rng(n)
+    g = gg.gnp(n, min(1.0, 6.0 / max(n - 1, 1)), 500 + n)
+    check_plus(g, rng.permutation(n).astype(np.int32), tag="boundary gnp")
+    check_interval(gg.intervals(n, 6, 600 + n), tag="boundary unit")
+    check_interval(gg.intervals(n, 6, 700 + n, unit=False), tag="boundary mixed")
+
+
+def test_batch_at_team_boundaries():
+    """A batch whose sizes straddle the wavefront / workgroup threshold and
+    the chunk sizes of both team kinds."""
+    graphs = []
+    for n in BOUNDARY_SIZES:
+        graphs.append(gg.intervals(n, 6, 800 + n))
+        graphs.append(gg.intervals(n, 6, 900 + n, unit=False))
+    check_batch(graphs, "boundary sizes")
