@@ -99,3 +99,25 @@ def test_batch_forced_fallback():
         if not ref.chordal:
             cyc, fb = oracle.certificate(g, ref.order, ref.rank, ref.witness, force_fallback=True)
             assert r.cycle_list == cyc.tolist() and fb
+
+
+@pytest.mark.parametrize("n", [63, 65, 511, 513, 1023, 1025, 2049, 4095, 4097, 8193, 16385, 32769])
+def test_team_boundary_sizes(n):
+    """MCS on single graphs at team-size and chunk boundaries."""
+    check(gg.subtree(n, max(2, n // 4), 8, 6000 + n), tag="boundary")
+    check(gg.plant(gg.subtree(n - 9, max(2, n // 4), 8, 6001 + n), 9, 6002 + n), tag="boundary planted")
+    check(gg.gnp(n, 6.0 / (n - 1), 6003 + n), tag="boundary gnp")
+
+
+def test_batch_team_boundary_sizes():
+    graphs = []
+    for n in (63, 65, 511, 513, 1023, 1025, 2047, 2049, 4095, 4097, 8191, 8193):
+        graphs += [gg.subtree(n, max(2, n // 4), 8, 7000 + n), gg.plant(gg.subtree(n - 9, max(2, n // 4), 8, 7001 + n), 9, 7002 + n),
+                   gg.gnp(n, 6.0 / (n - 1), 7003 + n)]
+    say(f"[mcs] boundary batch count={len(graphs)}")
+    refs = [oracle.chordal_test(g, "mcs") for g in graphs]
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    for tuning in (None, {"wave_max_n": -1}):
+        rs = lx.chordal_test_batch(dgs, outputs=True, flags=MCS, tuning=tuning)
+        for g, r, ref in zip(graphs, rs, refs):
+            same(r, ref, g.name)

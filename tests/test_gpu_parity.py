@@ -337,3 +337,39 @@ def test_batch_large_tier_with_plan_and_one_shot():
             assert r.chordal == ref.chordal and r.witness == ref.witness, g.name
             assert r.cycle_list == ref.cycle.tolist(), g.name
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Sizes around every team-size, chunk and layout boundary
+# ---------------------------------------------------------------------------
+
+BOUNDARY_SIZES = [63, 64, 65, 127, 129, 511, 512, 513, 1023, 1024, 1025, 2047, 2049, 4095, 4096, 4097, 8191,
+                  8193, 16383, 16385, 32767, 32769]
+
+
+def boundary_graphs(n, seed):
+    """A chordal graph, the same kind with a planted chordless 9-cycle, and a
+    sparse G(n, p), each with exactly n vertices."""
+    return [gg.subtree(n, max(2, n // 4), 8, seed), gg.plant(gg.subtree(n - 9, max(2, n // 4), 8, seed + 1), 9, seed + 2),
+            gg.gnp(n, min(1.0, 6.0 / (n - 1)), seed + 3)]
+
+
+@pytest.mark.parametrize("n", BOUNDARY_SIZES)
+def test_team_boundary_sizes(n):
+    """Single graphs at n = 2^k - 1, 2^k, 2^k + 1 (and chunk edges): every
+    team size the single-graph path picks, a partial last chunk and a last
+    bitset word holding one vertex."""
+    for g in boundary_graphs(n, 1000 + n):
+        check_single(g, tag="boundary")
+
+
+def test_batch_team_boundary_sizes():
+    """One batch holding every boundary size up to 8,193 (wavefront and
+    workgroup teams, rows of under and over 64 words side by side), under the
+    default and two other wavefront thresholds."""
+    graphs = []
+    for n in BOUNDARY_SIZES:
+        if n <= 8193:
+            graphs += boundary_graphs(n, 5000 + n)
+    for tuning in (None, {"wave_max_n": 256}, {"wave_max_n": -1}):
+        check_batch(graphs, tuning=tuning, tag="boundary sizes")
