@@ -522,7 +522,9 @@ def main():
     value = len(graphs) * args.steps / elapsed
     log(f"timed {args.steps} steps in {elapsed:.3f}s -> {value:.1f} tests/s")
     roof, per_kind = roofline_from(timing, args.steps, graphs, fused=args.workload == "batch")
-    roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+    # The committed counters were taken with the LexBFS ordering; the MCS
+    # kernel's traffic is not measured.
+    roof["traffic"] = measured_traffic(args.workload, roof["kernel"]) if args.ordering == "lexbfs" else None
 
     # ---------------- consecutive passes overlapped on two streams ----------------
     # (each stream with its own plan, workspace and outputs over the same
