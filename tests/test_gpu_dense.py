@@ -1,8 +1,9 @@
 """GPU parity on dense graphs (half or all of the possible edges): neighbour
 counts near n per class and per step, pivots that split every class, and
 rows with every word full. The sparse workloads never reach these counts.
-Chordality (LexBFS and MCS), LexBFS+ and the unit interval test, single
-graphs and batches, all element by element against the oracle."""
+Chordality (LexBFS, MCS and the per-step-launch form), LexBFS+ and the
+unit interval test, single graphs and batches, all element by element
+against the oracle."""
 import sys
 
 import numpy as np
@@ -54,6 +55,7 @@ def dense_cases():
 def test_dense_chordality(idx):
     g = dense_cases()[idx]
     check_single(g, tag="dense")
+    check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="dense, per-step launches")
     check_mcs(g, tag="dense")
 
 

@@ -3,9 +3,10 @@ followed by isolated vertices). When a pivot empties the top class, the
 class below is often a large class of untouched vertices whose start lies
 more than two bitmap words below the top position, so the step falls back to
 the team-wide scan of the class-start bitmap (a second reduction). Denser
-graphs almost never reach that path. Chordality (LexBFS and MCS), LexBFS+
-and the unit interval test, single graphs in every LexBFS layout and
-batches on wavefront and workgroup teams, against the oracle."""
+graphs almost never reach that path. Chordality (LexBFS, MCS and the
+per-step-launch form), LexBFS+ and the unit interval test, single graphs in
+every LexBFS layout and batches on wavefront and workgroup teams, against
+the oracle."""
 import sys
 
 import numpy as np
@@ -55,6 +56,8 @@ SINGLE = [(700, 1.0, 1), (1000, 0.5, 2), (3000, 1.5, 3), (9000, 2.0, 4), (25000,
 def test_sparse_single(n, deg, seed):
     g = sparse_gnp(n, deg, seed)
     check_single(g, tag="sparse")
+    if n <= 9000:
+        check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="sparse, per-step launches")
     check_mcs(g, tag="sparse")
 
 
@@ -63,6 +66,7 @@ def test_components_then_isolated(case):
     g = {"path": lambda: path_then_isolated(1500, 100), "clique": lambda: clique_then_isolated(2050, 50),
          "star": lambda: gg.from_edges(801, [(0, v) for v in range(1, 301)], "S300+E500")}[case]()
     check_single(g, tag="components")
+    check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag="components, per-step launches")
     check_mcs(g, tag="components")
     check_interval(g, tag="components")
 
