@@ -98,3 +98,20 @@ def test_sparse_interval_batch():
     graphs = [sparse_gnp(n, 1.0, 200 + n) for n in (100, 700, 1500, 3000)]
     graphs += [path_then_isolated(1500, 100), gg.intervals(2000, 1.0, 17), gg.intervals(900, 0.5, 18, unit=False)]
     check_interval_batch(graphs, "sparse")
+
+
+def test_batch_with_a_maximum_size_graph():
+    """A batch holding an n = 65,536 graph (the largest supported size: the
+    1,024-lane tier with its class tables in L2) beside small ones, for
+    LexBFS, MCS and the batched unit interval test."""
+    big = sparse_gnp(65536, 1.5, 300)
+    graphs = [big, sparse_gnp(900, 1.0, 301), sparse_gnp(3000, 1.5, 302), path_then_isolated(1500, 100)]
+    check_batch(graphs, tag="with n = 65536")
+    refs = [oracle.chordal_test(g, "mcs") for g in graphs]
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    say("[sparse] MCS batch with n = 65536")
+    rs = lx.chordal_test_batch(dgs, outputs=True, flags=lx.LEXBFS_FLAG_MCS)
+    for g, r, ref in zip(graphs, rs, refs):
+        assert np.array_equal(r.order.cpu().numpy(), ref.order), g.name
+        assert r.chordal == ref.chordal and r.witness == ref.witness, g.name
+    check_interval_batch(graphs, "with n = 65536")
