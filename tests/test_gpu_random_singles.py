@@ -3,8 +3,10 @@ plus (about one in seven) sparse G(n, p) or interval graphs of 12,000-65,536
 vertices, so that every single-graph LexBFS layout runs (LDS tables, compact,
 class tables in L2). Each graph: LexBFS and MCS results (order, parents,
 verdict, witness, certificate), the per-step-launch form up to n = 9,000,
-LexBFS+ after a random previous order, and the unit interval test, against
-the oracle. Seeded; `RANDOM_SINGLES` sets how many."""
+LexBFS+ after a random previous order, the unit interval test, and the
+bitset built on the device from the CSR (with padded rows) and the whole
+path from that CSR, against the oracle. Seeded; `RANDOM_SINGLES` sets how
+many."""
 import os
 import sys
 
@@ -60,3 +62,17 @@ def test_random_single(k):
     ref = oracle.unit_interval_test(g)
     assert r.unit_interval == ref.unit_interval and r.witness == ref.witness, "unit interval"
     assert np.array_equal(r.order.cpu().numpy(), ref.order), "unit interval order"
+    # Device-side ingestion: the bitset built from the CSR on the device (rows
+    # padded by a random number of words) and the whole path from that CSR.
+    if g.n > 0:
+        pad = int(rng.integers(0, 4))
+        W = (g.n + 63) // 64 + pad
+        rp = torch.from_numpy(g.row_ptr).to(DEV)
+        ci = torch.from_numpy(g.col_idx if g.col_idx.size else np.zeros(0, np.int32)).to(DEV)
+        bits = lx.build_bitset(g.n, rp, ci, W)
+        torch.cuda.synchronize()
+        got = bits.cpu().numpy().view(np.uint64)[: g.n * W].reshape(g.n, W)
+        assert np.array_equal(got, oracle.bitset_from_csr(g.n, g.row_ptr, g.col_idx, W)), "device bitset"
+        r = lx.chordal_test(lx.DeviceGraph.from_csr(g.n, rp, ci))
+        ref = oracle.chordal_test(g)
+        assert np.array_equal(r.order.cpu().numpy(), ref.order) and r.witness == ref.witness, "from device CSR"
