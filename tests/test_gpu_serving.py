@@ -68,3 +68,22 @@ def test_same_result_alone_and_in_mix():
         assert alone.chordal == r.result.chordal and alone.witness == r.result.witness
         assert alone.cycle_list == r.result.cycle_list
         assert torch.equal(alone.order, r.result.order)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_streams(seed):
+    """Requests drawn as in the random batch test (mixed families and
+    densities, sizes up to 12,000, some above the batch limit), random gaps
+    between arrivals, and a tight or a loose memory budget."""
+    from test_gpu_random_batches import rand_graph
+
+    rng = np.random.default_rng(7000 + seed)
+    count = int(rng.integers(10, 60))
+    graphs = [g for g in (rand_graph(rng, int(rng.integers(1, 1 << 30))) for _ in range(count)) if g.n > 0]
+    arr = np.cumsum(rng.exponential(rng.uniform(1e-5, 2e-3), len(graphs)))
+    big = max(serving.footprint_bytes(g.n, g.nnz, g.W) for g in graphs)
+    budget = int(big * rng.uniform(1.0, 1.5)) if rng.random() < 0.5 else 1 << 30
+    print(f"[serving] random stream {seed}: {len(graphs)} requests, budget {budget}", flush=True)
+    out = serving.serve(graphs, arr, budget_bytes=budget, outputs=True)
+    check(out, graphs)
+    assert out["peak_bytes"] <= budget
