@@ -431,7 +431,8 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the chordality path here runs on a single MI355X "
-              "(--gpus above 1 is not supported; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(--gpus above 1 is not supported; graphs are independent, so several GPUs would each take "
+              "a share of the batch, longest graphs first)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
