@@ -132,12 +132,21 @@ def mcs(g) -> OrderResult:
 
 def bitset_from_csr(n: int, row_ptr: np.ndarray, col_idx: np.ndarray, words_per_row: int) -> np.ndarray:
     """The packed adjacency bitset by its definition: bit u (word u // 64,
-    bit u % 64) of row v is set iff u is in v's CSR row; uint64[n, W]."""
+    bit u % 64) of row v is set iff u is in v's CSR row; uint64[n, W].
+    A CSR that names a vertex outside 0..n-1, or whose row pointers are not
+    a non-decreasing sequence from 0, describes no graph on n vertices
+    (Section 3.1): ValueError."""
+    if words_per_row < (n + 63) // 64:
+        raise ValueError("words_per_row below ceil(n / 64)")
+    rp = np.asarray(row_ptr[: n + 1], dtype=np.int64)
+    if len(rp) != n + 1 or (n >= 0 and rp[0] != 0) or np.any(np.diff(rp) < 0) or rp[-1] > len(col_idx):
+        raise ValueError("row pointers are not a non-decreasing sequence from 0 within col_idx")
     bits = np.zeros((n, words_per_row), dtype=np.uint64)
-    rows = np.repeat(np.arange(n), np.diff(np.asarray(row_ptr[: n + 1], dtype=np.int64)))
+    rows = np.repeat(np.arange(n), np.diff(rp))
     cols = np.asarray(col_idx[: len(rows)], dtype=np.int64)
-    keep = cols < 64 * words_per_row
-    np.bitwise_or.at(bits, (rows[keep], cols[keep] // 64), np.left_shift(np.uint64(1), (cols[keep] % 64).astype(np.uint64)))
+    if cols.size and (cols.min() < 0 or cols.max() >= n):
+        raise ValueError("a column index names a vertex outside 0..n-1")
+    np.bitwise_or.at(bits, (rows, cols // 64), np.left_shift(np.uint64(1), (cols % 64).astype(np.uint64)))
     return bits
 
 

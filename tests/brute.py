@@ -19,6 +19,10 @@ of neighbour sets ``adj`` over vertices 0..n-1.
   N[v*] enumerated explicitly, the one whose reversed vertex sequence is
   lexicographically smallest selected.
 * :func:`is_chordless_cycle` -- validity of a certificate.
+* :func:`parents_by_definition` -- p(v), the latest earlier neighbour.
+* :func:`three_sweeps_by_labels`, :func:`unit_interval_witness_by_definition`
+  -- the third order of the unit interval test from three label-string
+  sweeps, and its witness rule written out step by step.
 """
 from __future__ import annotations
 
@@ -68,6 +72,57 @@ def lexbfs_plus_by_labels(n: int, adj: Sequence[Set[int]], prev: Sequence[int]) 
             if not numbered[y]:
                 label[y] = label[y] + [n - i]
     return order
+
+
+def parents_by_definition(order: Sequence[int], adj: Sequence[Set[int]]) -> List[int]:
+    """p(v) of Section 5.2 for every vertex: the neighbour of v that comes
+    latest among those before v in `order`, or -1."""
+    pos = {v: i for i, v in enumerate(order)}
+    par = [-1] * len(order)
+    for v in order:
+        earlier = [u for u in adj[v] if pos[u] < pos[v]]
+        if earlier:
+            par[v] = max(earlier, key=lambda u: pos[u])
+    return par
+
+
+def three_sweeps_by_labels(n: int, adj: Sequence[Set[int]]) -> List[int]:
+    """The third order of the three-sweep unit interval test, every sweep
+    taken with literal label strings: LexBFS (smallest id on ties), then
+    LexBFS+ after it, then LexBFS+ after that."""
+    s1 = lexbfs_by_labels(n, adj)
+    s2 = lexbfs_plus_by_labels(n, adj, s1)
+    return lexbfs_plus_by_labels(n, adj, s2)
+
+
+def unit_interval_witness_by_definition(order: Sequence[int], adj: Sequence[Set[int]]):
+    """The witness of a failed unit interval test, written out from its
+    definition: walk the order from the front; the first vertex v whose
+    closed neighbourhood does not occupy consecutive positions is the
+    failing one. Its closed neighbourhood spans positions lo..hi; b is the
+    vertex at the first position of that span that is neither v nor a
+    neighbour of v. When b is placed before v the triple is
+    (order[lo], b, v), otherwise (v, b, order[hi]). None if every closed
+    neighbourhood is consecutive."""
+    where = {}
+    for i, v in enumerate(order):
+        where[v] = i
+    for i, v in enumerate(order):
+        closed = set(adj[v])
+        closed.add(v)
+        spots = sorted(where[u] for u in closed)
+        lo, hi = spots[0], spots[-1]
+        if hi - lo + 1 == len(spots):
+            continue
+        b = None
+        for j in range(lo, hi + 1):
+            if order[j] not in closed:
+                b = order[j]
+                break
+        if where[b] < i:
+            return (order[lo], b, v)
+        return (v, b, order[hi])
+    return None
 
 
 def closed_nbhds_consecutive(order: Sequence[int], adj: Sequence[Set[int]]) -> bool:

@@ -151,6 +151,13 @@ PY_MUTANTS = [
      "        ps = np.concatenate([pos[nbrs], [i]])\n", "        ps = pos[nbrs] if len(nbrs) else np.array([i])\n"),
     ("two sweeps instead of three",
      "    s3 = lexbfs_plus(g, s2).order\n", "    s3 = s2\n"),
+    ("witness b = the latest instead of the earliest non-member of the span",
+     "        b_pos = lo + int(np.argmin(inside))\n",
+     "        b_pos = hi - int(np.argmin(inside[::-1]))\n"),
+    ("witness triple forms swapped",
+     "        if b_pos < i:\n", "        if b_pos > i:\n"),
+    ("witness orientation by the middle of the span instead of by v",
+     "        if b_pos < i:\n", "        if 2 * b_pos < lo + hi:\n"),
 ]
 
 

@@ -315,3 +315,21 @@ def test_bitset_from_csr_matches_the_generators_and_a_hand_example():
         assert np.array_equal(b, g.bits.reshape(g.n, g.W)), g.name
     b = orc.bitset_from_csr(70, np.array([0, 1] + [1] * 68 + [2], dtype=np.int32), np.array([69, 0], dtype=np.int32), 2)
     assert b[0, 1] == np.uint64(1 << 5) and b[69, 0] == np.uint64(1) and int(b.sum()) == (1 << 5) + 1
+
+
+def test_bitset_from_csr_rejects_what_is_no_graph():
+    """Ids outside 0..n-1 (even inside the row's padding words) and broken
+    row pointers describe no graph on n vertices: rejected, not dropped."""
+    import oracle as orc
+
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    with pytest.raises(ValueError):
+        orc.bitset_from_csr(2, rp, np.array([1, 2], dtype=np.int32), 1)     # id n, inside the word
+    with pytest.raises(ValueError):
+        orc.bitset_from_csr(2, rp, np.array([1, 64], dtype=np.int32), 2)    # id in a padding word
+    with pytest.raises(ValueError):
+        orc.bitset_from_csr(2, rp, np.array([1, -1], dtype=np.int32), 1)    # negative id
+    with pytest.raises(ValueError):
+        orc.bitset_from_csr(2, np.array([0, 2, 1], dtype=np.int32), np.array([1, 0], dtype=np.int32), 1)
+    with pytest.raises(ValueError):
+        orc.bitset_from_csr(70, np.zeros(71, dtype=np.int32), np.zeros(0, dtype=np.int32), 1)  # W too small
