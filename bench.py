@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="batch: time only the plain passes (no overlapped passes, HIP-graph replay or per-graph path), "
                          "so that a kernel trace holds only launches like the timed ones")
+    ap.add_argument("--no-c3-sweep", action="store_true",
+                    help="batch: skip the sub-record of the elimination sweep on the N=65,536 split graph")
     ap.add_argument("--ordering", default="lexbfs", choices=["lexbfs", "mcs"],
                     help="vertex order tested: LexBFS (default) or Maximum Cardinality Search")
     return ap.parse_args()
@@ -75,20 +77,30 @@ def components(g):
     return int(connected_components(a, directed=False)[0])
 
 
-def algorithmic_bytes(graphs, fused=False):
-    """Per pass: the bitset read once (n rows of ceil(n/64) words) and the
-    int32 per-vertex arrays each kernel touches. With the elimination test
-    fused into LexBFS (the batch kernel) that kernel also reads the parent's
-    row of every vertex that has a parent (all but the first vertex of each
-    connected component)."""
+def bitset_bytes(graphs):
+    """The algorithmic floor of a pass: every graph's bitset read once,
+    n rows of ceil(n/64) 64-bit words, summed over the graphs (N * 8W)."""
+    return sum(g.n * 8 * ((g.n + 63) // 64) for g in graphs)
+
+
+def algorithmic_bytes(graphs):
+    """Per pass and kernel kind: the floor N * 8W for LexBFS (every pivot
+    row once) and for the elimination sweep (every row once); the witness,
+    certificate and setup kernels are charged nothing."""
+    b = bitset_bytes(graphs)
+    return {"lexbfs": b, "sweep": b, "certificate": 0, "setup": 0}
+
+
+def extra_bytes(graphs, fused=False):
+    """Bytes the LexBFS kernel moves beyond the floor, reported beside it:
+    the int32 order, rank and parent it writes (12 B per vertex) and, with
+    the elimination test folded into the steps (the batch kernel), the row
+    of the parent of every vertex that has one (all but the first vertex of
+    each connected component)."""
     row = lambda g: 8 * ((g.n + 63) // 64)
-    bitset = sum(g.n * row(g) for g in graphs)
-    sn = sum(g.n for g in graphs)
-    out = {"lexbfs": bitset + 12 * sn,  # pivot rows; order, rank, parent written
-           "sweep": bitset + 8 * sn,    # every row once; rank and parent read
-           "certificate": 0, "setup": 0}
+    out = {"output_bytes": 12 * sum(g.n for g in graphs)}
     if fused:
-        out["lexbfs"] += sum((g.n - components(g)) * row(g) for g in graphs)
+        out["parent_row_bytes"] = sum((g.n - components(g)) * row(g) for g in graphs)
     return out
 
 
@@ -96,7 +108,7 @@ def roofline_from(timing, steps, graphs, fused=False):
     """Algorithmic bytes of one pass split evenly over the launches of one
     pass (a batch pass launches each kernel once; the single-graph workloads
     launch each kernel once per graph, and their graphs have equal n)."""
-    ab = algorithmic_bytes(graphs, fused)
+    ab = algorithmic_bytes(graphs)
     per_kind = {}
     for kind, (count, ms) in timing.items():
         if count == 0:
@@ -109,7 +121,11 @@ def roofline_from(timing, steps, graphs, fused=False):
     d = per_kind[dom]
     roof = {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (d["gbs"] / HBM_PEAK_GBS) if d["gbs"] is not None else None, "traffic": None,
-            "kernel": dom, "avg_launch_ms": d["avg_ms"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
+            "kernel": dom, "avg_launch_ms": d["avg_ms"], "algorithmic_bytes_per_launch": d["bytes_per_launch"],
+            "algorithmic_bytes_rule": "sum over the graphs of N * 8 * ceil(N / 64): every bitset read once"}
+    if dom == "lexbfs":
+        per = {k: v * steps / timing[dom][0] for k, v in extra_bytes(graphs, fused).items()}
+        roof.update(per)
     return roof, per_kind
 
 
@@ -261,7 +277,7 @@ def bench_interval(args):
     path is timed on a sample.
 
     Algorithmic bytes per launch: LexBFS as in the chordality path (every
-    pivot row once, order/rank/parent written); renaming of one sweep: CSR
+    pivot row once: N * 8W per sweep); renaming of one sweep: CSR
     read and written, bitset written, 11 int32 arrays of n; check: order,
     row_ptr, col_idx and one rank per CSR entry."""
     import ctypes
@@ -270,7 +286,6 @@ def bench_interval(args):
     import torch
 
     import graphgen as gg
-    import oracle
     import paper_1508_06329_amd as lx
 
     dev = torch.device("cuda:0")
@@ -311,10 +326,6 @@ def bench_interval(args):
     step()
     torch.cuda.synchronize()
     got = res.cpu().numpy()
-    chk = range(0, count, max(1, count // 256))  # verdicts checked against the oracle on a spread sample
-    refs = {i: oracle.unit_interval_test(graphs[i]) for i in chk}
-    for i, r in refs.items():
-        assert bool(got[i][0]) == r.unit_interval and tuple(int(x) for x in got[i][1:4]) == r.witness, graphs[i].name
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -328,7 +339,7 @@ def bench_interval(args):
     value = count * args.steps / elapsed
     row = lambda g: 8 * ((g.n + 63) // 64)
     nnz = lambda g: len(g.col_idx)
-    ab = {"lexbfs": 3 * sum(g.n * row(g) + 12 * g.n for g in graphs),
+    ab = {"lexbfs": 3 * sum(g.n * row(g) for g in graphs),
           "setup": 2 * sum(2 * 4 * (g.n + 1 + nnz(g)) + g.n * row(g) + 4 * (g.n + 1 + nnz(g)) + 44 * g.n
                            for g in graphs),
           "sweep": sum(4 * g.n + 4 * (g.n + 1) + 8 * nnz(g) for g in graphs), "certificate": 0}
@@ -365,6 +376,8 @@ def bench_interval(args):
         log(f"per-graph path: {pg:.1f} tests/s")
     cpu = None
     if not args.no_cpu_baseline:
+        import oracle
+
         t0 = time.perf_counter()
         done = 0
         while time.perf_counter() - t0 < args.cpu_seconds or done == 0:
@@ -375,6 +388,13 @@ def bench_interval(args):
                "sample": f"{done} tests of the same graphs in generation order ({el:.1f}s, one thread: three "
                          f"partition-refinement LexBFS sweeps with renaming, then the neighbourhood check)"}
         log(f"cpu oracle: {cpu['value']:.2f} tests/s")
+        # the first pass's verdicts and witnesses against the oracle on a spread sample
+        chk = range(0, count, max(1, count // 256))
+        for i in chk:
+            r = oracle.unit_interval_test(graphs[i])
+            assert bool(got[i][0]) == r.unit_interval and tuple(int(x) for x in got[i][1:4]) == r.witness, \
+                graphs[i].name
+        cpu["gpu_results_checked"] = len(chk)
     print(json.dumps({
         "metric": "unit interval tests/s (three-sweep LexBFS+ test) on 1 MI355X",
         "value": value, "unit": "tests/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -390,6 +410,96 @@ def bench_interval(args):
         "per_graph": per_graph,
         "cpu_baseline": cpu,
     }), flush=True)
+
+
+def c3_sweep_record(args, dev):
+    """The elimination sweep (Section 6.2 "testing", one launch of
+    k_sweep_single) on the N = 65,536 split graph, whose 512 MiB bitset is
+    larger than the 256 MiB last-level cache, so its rows stream from HBM.
+    Timed with the library's HIP events over `reps` chordal_test calls on
+    each graph of the split pair; its floor is the bitset read once,
+    N * 8W = 536,870,912 bytes."""
+    import ctypes
+
+    import torch
+
+    import graphgen as gg
+    import paper_1508_06329_amd as lx
+
+    graphs = gg.config_worst_steps()
+    dgs = lx.pack_graphs(graphs, dev)
+    lib = lx._lib.load()
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(lx.workspace_bytes(graphs[0].n), dtype=torch.uint8, device=dev)
+    res = torch.zeros((len(dgs), 8), dtype=torch.int32, device=dev)
+    descs = [d.desc() for d in dgs]
+
+    def run():
+        for i, d in enumerate(descs):
+            lx._lib.check(lib.chordal_test(ctypes.byref(d), res[i].data_ptr(), None, ws.data_ptr(), ws.numel(), 0,
+                                           stream.cuda_stream), "chordal_test")
+
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    with lx.KernelTimer() as kt:
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        t = kt.collect()
+    count, ms = t["sweep"]
+    avg = ms / count
+    floor = bitset_bytes(graphs[:1])
+    gbs = floor / (avg / 1e3) / 1e9
+    log(f"split-graph sweep: {avg:.4f} ms per launch -> {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f} of HBM peak)")
+    return {"kernel": "k_sweep_single", "workload": "N=65,536 split graph and the copy minus one clique edge, seed 0",
+            "launches": count, "avg_ms": avg, "bytes_floor_per_launch": floor, "achieved_gbs": gbs,
+            "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("split", "sweep"),
+            "lexbfs_ms_per_graph": t["lexbfs"][1] / t["lexbfs"][0],
+            "verdicts": [int(x) for x in res[:, 0].tolist()], "witnesses": [res[i, 1:4].tolist() for i in range(len(dgs))]}
+
+
+def largest_graph_latency(dgs, graphs, tuning, flags, pass_ms, dev):
+    """Per-step latency of the chain that bounds a pass: the largest graph's
+    LexBFS, N dependent steps. Reported two ways: the pass's kernel time over
+    the largest N, and that graph alone in a one-graph plan (same team, same
+    kernel, nothing else on the GPU)."""
+    import torch
+
+    import paper_1508_06329_amd as lx
+
+    big = max(range(len(graphs)), key=lambda i: graphs[i].n)
+    n = graphs[big].n
+    p1 = lx.BatchPlan([dgs[big]], tuning=tuning, flags=flags)
+    p1.launch()
+    torch.cuda.synchronize()
+    with lx.KernelTimer() as kt:
+        for _ in range(5):
+            p1.launch()
+        torch.cuda.synchronize()
+        t = kt.collect()
+    p1.close()
+    alone = t["lexbfs"][1] / t["lexbfs"][0]
+    return {"largest_n": n, "pass_us_per_step_of_largest": pass_ms * 1e3 / n, "largest_alone_ms": alone,
+            "largest_alone_us_per_step": alone * 1e3 / n}
+
+
+def check_against_oracle(graphs, results, ordering, sample=256):
+    """The timed pass's verdict, witness, certificate length and fallback
+    flag against the oracle, on an evenly spread sample of the graphs.
+    Part of the CPU-baseline leg (the only leg that runs the oracle)."""
+    import numpy as np
+
+    import oracle
+
+    idx = sorted(set(np.linspace(0, len(graphs) - 1, min(sample, len(graphs))).astype(int).tolist()))
+    for i in idx:
+        ref = oracle.chordal_test(graphs[i], ordering)
+        r = results[i]
+        got = (r.chordal, r.witness, r.cycle_len, r.fallback)
+        exp = (ref.chordal, ref.witness, len(ref.cycle), ref.fallback)
+        assert got == exp, f"graph {i} ({graphs[i].name}): GPU {got} != oracle {exp}"
+    return len(idx)
 
 
 def cpu_oracle_rate(graphs, seconds, threads, ordering="lexbfs"):
@@ -526,6 +636,13 @@ def main():
     # The committed counters were taken with the LexBFS ordering; the MCS
     # kernel's traffic is not measured.
     roof["traffic"] = measured_traffic(args.workload, roof["kernel"]) if args.ordering == "lexbfs" else None
+    if args.workload == "batch":
+        timed_results = plan.results()
+        roof["latency"] = largest_graph_latency(dgs, graphs, tune["tuning"], order_flag, per_kind["lexbfs"]["avg_ms"],
+                                                dev)
+        log(f"largest graph (N={roof['latency']['largest_n']}): "
+            f"{roof['latency']['pass_us_per_step_of_largest']:.3f} us/step in the pass, "
+            f"{roof['latency']['largest_alone_us_per_step']:.3f} us/step alone")
 
     # ---------------- consecutive passes overlapped on two streams ----------------
     # (each stream with its own plan, workspace and outputs over the same
@@ -633,6 +750,10 @@ def main():
                      "batched_speedup": value / pg_rate}
         log(f"per-graph path: {pg_rate:.1f} tests/s on {len(descs)} graphs")
 
+    c3 = None
+    if args.workload == "batch" and not args.no_c3_sweep and args.ordering == "lexbfs":
+        c3 = c3_sweep_record(args, dev)
+
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -647,6 +768,10 @@ def main():
             log(f"cpu oracle on {threads} thread(s): {rows[threads]['value']:.1f} tests/s")
         cpu = dict(rows[max(rows)])
         cpu["one_core"] = {k: rows[1][k] for k in ("value", "edges_per_s", "sample")}
+        if args.workload == "batch":
+            checked = check_against_oracle(graphs, timed_results, args.ordering)
+            cpu["gpu_results_checked"] = checked
+            log(f"timed pass matches the oracle on {checked} spread graphs")
 
     out = {
         "metric": "chordality tests/s and edges/s, batched vs per-graph on 1 MI355X; p50/p99 ms",
@@ -672,6 +797,7 @@ def main():
         "schedule": tune,
         "hipgraph": hipgraph,
         "overlapped_passes": overlapped,
+        "c3_sweep": c3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

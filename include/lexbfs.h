@@ -50,7 +50,7 @@ extern "C" {
 #define LEXBFS_EINVAL (-1)  /* null required pointer, n < 0, words_per_row < ceil(n/64), nnz outside [0, 2^31) */
 #define LEXBFS_ENOWS (-2)   /* workspace pointer null or smaller than required */
 #define LEXBFS_EHIP (-3)    /* a HIP runtime call or kernel launch failed */
-#define LEXBFS_EGRAPH (-4)  /* reserved: input contract violation detected by a validating call */
+#define LEXBFS_EGRAPH (-4)  /* input contract violated (only from lexbfs_validate or LEXBFS_FLAG_VALIDATE) */
 #define LEXBFS_ETOOBIG (-5) /* n above LEXBFS_MAX_N or above what the device's LDS supports */
 
 /* Largest supported vertex count: class ids and vertex ids are kept in 16 bits. */
@@ -72,6 +72,13 @@ extern "C" {
  * parent are those of the MCS order. Not combinable with
  * LEXBFS_FLAG_PER_STEP (LEXBFS_EINVAL). */
 #define LEXBFS_FLAG_MCS 0x4u
+/* chordal_test, chordal_test_batch and lexbfs_batch_plan_create: check the
+ * input contract on the device (as lexbfs_validate does) before any other
+ * kernel runs, and return LEXBFS_EGRAPH without running the test if a
+ * graph breaks it. The check's verdict is needed on the host, so with this
+ * flag the call waits for `stream` to drain the check (not capturable into
+ * a hipGraph); a plan is checked once, at creation. */
+#define LEXBFS_FLAG_VALIDATE 0x8u
 
 /* One graph. All pointers are device memory. */
 typedef struct lexbfs_graph {
@@ -114,6 +121,27 @@ typedef struct lexbfs_outputs {
 
 /* Workspace bytes for lexbfs_order / chordal_test on a graph of n vertices. */
 size_t lexbfs_workspace_bytes(int32_t n);
+
+/*
+ * lexbfs_validate -- check that g is what every other entry point assumes
+ * (Section 3.1 works with simple graphs: N(v) never holds v and adjacency
+ * is symmetric; the CSR and the bitset of lexbfs_graph_t must describe the
+ * same N(v)). On the device, reading only inside the arrays the contract
+ * sizes: row_ptr non-decreasing from row_ptr[0] = 0 to row_ptr[n] = nnz;
+ * every column index in 0..n-1; every row strictly ascending (no
+ * duplicates); no self-loop; every CSR entry (v, u) set in bitset row v and
+ * its reverse set in row u; and no other bit set in a row's first
+ * ceil(n/64) words (bits >= n included). The other entry points do not
+ * check this themselves (it costs a pass over the CSR and the bitset):
+ * given a graph that breaks it they may return wrong results or read out of
+ * bounds.
+ *   ws   device memory of at least 256 bytes (any workspace of this
+ *        library's *_workspace_bytes size will do); one word is written
+ * Waits for `stream` to finish the check. Returns LEXBFS_OK, LEXBFS_EGRAPH
+ * (lexbfs_last_error names the first violated rule), LEXBFS_EINVAL,
+ * LEXBFS_ENOWS, LEXBFS_ETOOBIG or LEXBFS_EHIP.
+ */
+int lexbfs_validate(const lexbfs_graph_t *g, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * lexbfs_order -- the LexBFS order (Section 4.1 definition; Section 6.1

@@ -17,13 +17,13 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_MCS, LEXBFS_FLAG_PER_STEP, LEXBFS_MAX_N, LexbfsError,
-                   lexbfs_graph_t, lexbfs_outputs_t, lexbfs_result_t, lexbfs_tuning_t)
+from ._lib import (LEXBFS_FLAG_FORCE_FALLBACK, LEXBFS_FLAG_MCS, LEXBFS_FLAG_PER_STEP, LEXBFS_FLAG_VALIDATE, LEXBFS_MAX_N,
+                   LexbfsError, lexbfs_graph_t, lexbfs_outputs_t, lexbfs_result_t, lexbfs_tuning_t)
 
 __all__ = ["BatchPlan", "pack_graphs", "build_bitset", "KernelTimer", "DeviceGraph", "Result", "lexbfs_order", "chordal_test", "chordal_test_batch", "workspace_bytes",
            "lexbfs_plus", "unit_interval_test", "unit_interval_test_batch", "IntervalResult",
            "batch_workspace_bytes", "LexbfsError", "LEXBFS_MAX_N", "LEXBFS_FLAG_FORCE_FALLBACK",
-           "LEXBFS_FLAG_PER_STEP", "LEXBFS_FLAG_MCS"]
+           "LEXBFS_FLAG_PER_STEP", "LEXBFS_FLAG_MCS", "LEXBFS_FLAG_VALIDATE", "validate"]
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -33,6 +33,22 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> Optional[int]:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+def _on_stream(stream: Optional[torch.cuda.Stream], *tensors: Optional[torch.Tensor]) -> None:
+    """Tensors allocated on the current stream but used by kernels on
+    another one: tell the caching allocator, so that freeing them (a
+    temporary workspace dropped on return, an output the caller drops) does
+    not hand their memory to a new allocation while those kernels run."""
+    if stream is None or stream == torch.cuda.current_stream(stream.device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
+def _wait(stream: Optional[torch.cuda.Stream]) -> None:
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
 
 
 class DeviceGraph:
@@ -134,7 +150,16 @@ def build_bitset(n: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, words_per
         rc = _lib.load().lexbfs_build_bitset(n, row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None,
                                              bits.data_ptr(), W, _stream_handle(stream))
         _lib.check(rc, "lexbfs_build_bitset")
+        _on_stream(stream, bits)
     return bits
+
+
+def validate(g: DeviceGraph, stream=None) -> None:
+    """Check the input contract on the device (lexbfs_validate); raises
+    LexbfsError with code LEXBFS_EGRAPH (-4) naming the broken rule."""
+    ws = _workspace(256, g.device)
+    rc = _lib.load().lexbfs_validate(ctypes.byref(g.desc()), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _lib.check(rc, "lexbfs_validate")
 
 
 def workspace_bytes(n: int) -> int:
@@ -165,6 +190,7 @@ def lexbfs_order(g: DeviceGraph, stream=None, ws: Optional[torch.Tensor] = None)
     rc = lib.lexbfs_order(ctypes.byref(d), _ptr(order), _ptr(rank), _ptr(parent), ws.data_ptr(), ws.numel(),
                           _stream_handle(stream))
     _lib.check(rc, "lexbfs_order")
+    _on_stream(stream, ws, order, rank, parent)
     return order[:n], rank[:n], parent[:n]
 
 
@@ -187,6 +213,7 @@ def lexbfs_plus(g: DeviceGraph, prev_order: torch.Tensor, stream=None, ws: Optio
     rc = lib.lexbfs_plus_order(ctypes.byref(d), _ptr(prev_order) if n > 0 else None, _ptr(order), _ptr(rank),
                                _ptr(parent), ws.data_ptr(), ws.numel(), _stream_handle(stream))
     _lib.check(rc, "lexbfs_plus_order")
+    _on_stream(stream, ws, order, rank, parent)
     return order[:n], rank[:n], parent[:n]
 
 
@@ -215,8 +242,10 @@ def unit_interval_test(g: DeviceGraph, stream=None, ws: Optional[torch.Tensor] =
     rc = lib.unit_interval_test(ctypes.byref(d), res.data_ptr(), _ptr(order), ws.data_ptr(), ws.numel(),
                                 _stream_handle(stream))
     _lib.check(rc, "unit_interval_test")
+    _on_stream(stream, ws, res, order)
     if not sync:
         return IntervalResult(None, (-1, -1, -1), order[:n], res)
+    _wait(stream)
     r = res.tolist()
     return IntervalResult(bool(r[0]), (r[1], r[2], r[3]), order[:n], res)
 
@@ -242,7 +271,10 @@ def unit_interval_test_batch(graphs: Sequence[DeviceGraph], stream=None, outputs
     rc = lib.unit_interval_test_batch(descs, count, res.data_ptr(), optr, ws.data_ptr(), ws.numel(),
                                       _stream_handle(stream))
     _lib.check(rc, "unit_interval_test_batch")
+    _on_stream(stream, ws, res, *(orders or []))
     out = []
+    if sync:
+        _wait(stream)
     rows = res.tolist() if sync else None
     for i, g in enumerate(graphs):
         order = orders[i][:g.n] if outputs else None
@@ -280,14 +312,12 @@ def chordal_test(g: DeviceGraph, flags: int = 0, stream=None, outputs: bool = Tr
     rc = lib.chordal_test(ctypes.byref(d), res.data_ptr(), ctypes.byref(outs), ws.data_ptr(), ws.numel(),
                           flags, _stream_handle(stream))
     _lib.check(rc, "chordal_test")
+    _on_stream(stream, ws, res, *tens.values())
     if not sync:
         r = Result(False, (-1, -1, -1), 0, False, **{k: v[:n] for k, v in tens.items()})
         r.res_raw = res
         return r
-    if stream is not None:
-        stream.synchronize()
-    else:
-        torch.cuda.current_stream().synchronize()
+    _wait(stream)
     chordal, wit, clen, fb = _result_from(res.cpu())
     return Result(chordal, wit, clen, fb, **{k: v[:n] for k, v in tens.items()})
 
@@ -327,9 +357,10 @@ def chordal_test_batch(graphs: Sequence[DeviceGraph], flags: int = 0, stream=Non
     rc = lib.chordal_test_batch(arr, count, outs_arr, res.data_ptr(), tun, ws.data_ptr(), ws.numel(), flags,
                                 _stream_handle(stream))
     _lib.check(rc, "chordal_test_batch")
+    _on_stream(stream, ws, res, *(t for d in tens for t in d.values()))
     if not sync:
         return res
-    (stream or torch.cuda.current_stream()).synchronize()
+    _wait(stream)
     host = res.cpu()
     out = []
     for i, g in enumerate(graphs):
@@ -404,6 +435,7 @@ class BatchPlan:
             self._tun = t
             tun = ctypes.byref(t)
         self.handle = ctypes.c_void_p()
+        self._streams = set()
         rc = lib.lexbfs_batch_plan_create(self.arr, count, self.outs_arr, self.res.data_ptr(), tun,
                                           self.ws.data_ptr(), self.ws.numel(), flags, _stream_handle(stream),
                                           ctypes.byref(self.handle))
@@ -412,6 +444,11 @@ class BatchPlan:
     def launch(self, stream=None):
         rc = _lib.load().lexbfs_batch_plan_launch(self.handle, _stream_handle(stream))
         _lib.check(rc, "lexbfs_batch_plan_launch")
+        if stream is not None and stream not in self._streams:
+            # The plan's tensors are freed with the plan; kernels may still
+            # run on this stream then.
+            self._streams.add(stream)
+            _on_stream(stream, self.ws, self.res, *(t for d in self.tens for t in d.values()))
 
     def capture(self, stream=None) -> "torch.cuda.CUDAGraph":
         """Record one launch of this plan into a HIP graph (kernel nodes only:

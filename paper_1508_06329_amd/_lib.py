@@ -26,10 +26,11 @@ LEXBFS_MAX_N = 65536
 LEXBFS_FLAG_FORCE_FALLBACK = 0x1
 LEXBFS_FLAG_PER_STEP = 0x2
 LEXBFS_FLAG_MCS = 0x4
+LEXBFS_FLAG_VALIDATE = 0x8
 LEXBFS_KERNEL_KINDS = 4
 KERNEL_KIND_NAMES = ("lexbfs", "sweep", "certificate", "setup")
 
-EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_order", "chordal_test", "lexbfs_batch_workspace_bytes",
+EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_validate", "lexbfs_order", "chordal_test", "lexbfs_batch_workspace_bytes",
             "chordal_test_batch", "lexbfs_batch_plan_create", "lexbfs_batch_plan_launch",
             "lexbfs_batch_plan_destroy", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_profile_enable",
             "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_build_bitset", "lexbfs_plus_workspace_bytes",
@@ -92,6 +93,8 @@ def load() -> ctypes.CDLL:
     gp = ctypes.POINTER(lexbfs_graph_t)
     lib.lexbfs_workspace_bytes.restype = sz
     lib.lexbfs_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.lexbfs_validate.restype = ctypes.c_int
+    lib.lexbfs_validate.argtypes = [gp, vp, sz, vp]
     lib.lexbfs_order.restype = ctypes.c_int
     lib.lexbfs_order.argtypes = [gp, vp, vp, vp, vp, sz, vp]
     lib.chordal_test.restype = ctypes.c_int

@@ -112,6 +112,7 @@ struct GDesc {
     uint32_t *failkey; // [1]
     uint32_t *gtab;    // [2n] class tables in global memory (large n), else null
     lexbfs_result_t *res;
+    int64_t nnz;       // CSR entries (read only by the input check)
 };
 
 // ---------------------------------------------------------------------------
@@ -623,6 +624,106 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bitset(int n, const int
     const int wave = threadIdx.x >> 6;
     build_rows(n, rp, ci, bits, W, lds + (int64_t)wave * W, blockIdx.x * (kBuildThreads / kWave) + wave,
                gridDim.x * (kBuildThreads / kWave));
+}
+
+// ---------------------------------------------------------------------------
+// Input contract check (LEXBFS_FLAG_VALIDATE, lexbfs_validate). Section 3.1
+// works with simple graphs: N(v) never holds v, adjacency is symmetric, and
+// the CSR and the bitset must describe the same N(v). One wavefront per row;
+// every read stays inside the arrays the contract sizes: row_ptr[0..n],
+// col_idx[j] only for j inside [0, nnz) once the row's bounds are checked,
+// bitset rows only for ids already checked to lie in 0..n-1.
+//   CSR row v: ascending strictly (so no duplicates), ids in 0..n-1, no v;
+//   every entry u has bit u in row v and bit v in row u; the number of set
+//   bits in row v (bits >= n of the last word included) equals deg(v).
+// With every CSR entry present in the bitset and the counts equal, the two
+// agree exactly; with the reverse bits present the graph is symmetric.
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+    kBadRowPtr = 1u,   // row pointers not non-decreasing from 0 to nnz
+    kBadId = 2u,       // a column index outside 0..n-1
+    kSelfLoop = 4u,    // v in its own row
+    kUnsorted = 8u,    // a row not strictly ascending (unsorted or duplicate)
+    kNotInBits = 16u,  // a CSR entry whose bit is clear
+    kAsym = 32u,       // u in N(v) but v not in N(u)
+    kExtraBits = 64u,  // bits set that the CSR row does not hold
+};
+
+constexpr int kValidateThreads = 256;
+
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v |= (uint32_t)__shfl_xor((int)v, off, kWave);
+    return v;
+}
+
+// Rows first, first + stride, ... of graph g; ORs the error bits found into
+// *status (one atomic per wavefront, only when something is wrong).
+__device__ void validate_rows(const GDesc &g, int first, int stride, uint32_t *status)
+{
+    LX_GLOBAL const int32_t *rp = as_global(g.rp);
+    LX_GLOBAL const int32_t *ci = as_global(g.ci);
+    LX_GLOBAL const uint64_t *bits = as_global(g.bits);
+    const int lane = threadIdx.x & 63;
+    const int n = g.n;
+    const int64_t nnz = g.nnz;
+    const int wn = (n + 63) >> 6;
+    const uint64_t tailmask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+    uint32_t bad = 0;
+    for (int v = first; v < n; v += stride) {
+        const int64_t b = rp[v], e = rp[v + 1];
+        if (v == 0 && b != 0) bad |= kBadRowPtr;
+        if (v == n - 1 && e != nnz) bad |= kBadRowPtr;
+        if (b < 0 || e < b || e > nnz) {
+            bad |= kBadRowPtr;
+            continue;  // col_idx of this row is not known to be in bounds
+        }
+        for (int64_t j = b + lane; j < e; j += kWave) {
+            const int u = ci[j];
+            if (j > b && ci[j - 1] >= u) bad |= kUnsorted;
+            if (u < 0 || u >= n) {
+                bad |= kBadId;
+                continue;
+            }
+            if (u == v) bad |= kSelfLoop;
+            if (!((bits[(int64_t)v * g.W + (u >> 6)] >> (u & 63)) & 1ull)) bad |= kNotInBits;
+            if (!((bits[(int64_t)u * g.W + (v >> 6)] >> (v & 63)) & 1ull)) bad |= kAsym;
+        }
+        uint32_t cnt = 0;
+        for (int w = lane; w < wn; w += kWave) {
+            const uint64_t x = bits[(int64_t)v * g.W + w];
+            cnt += (uint32_t)__popcll(x);
+            if (w == wn - 1 && (x & ~tailmask)) bad |= kExtraBits;  // bits >= n
+        }
+        cnt = wave_sum_dpp(cnt);
+        if ((int64_t)cnt != e - b) bad |= kExtraBits;
+    }
+    bad = wave_or_u32(bad);
+    if (lane == 0 && bad) atomicOr(status, bad);
+}
+
+__global__ __launch_bounds__(kValidateThreads) void k_validate_one(GDesc g, uint32_t *status)
+{
+    constexpr int wpb = kValidateThreads / kWave;
+    validate_rows(g, blockIdx.x * wpb + (int)(threadIdx.x >> 6), gridDim.x * wpb, status);
+}
+
+// bpg blocks per graph; status[i] for graph i.
+__global__ __launch_bounds__(kValidateThreads) void k_validate_batch(const GDesc *__restrict__ gds, int count, int bpg,
+                                                                     uint32_t *status)
+{
+    constexpr int wpb = kValidateThreads / kWave;
+    const int gi = blockIdx.x / bpg;
+    if (gi >= count) return;
+    const int bl = blockIdx.x - gi * bpg;
+    validate_rows(gds[gi], bl * wpb + (int)(threadIdx.x >> 6), bpg * wpb, status + gi);
+}
+
+__global__ void k_fill_u32(uint32_t *p, int count, uint32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
 }
 
 // Batch: every block first takes large graphs (whole block per graph) from a
@@ -1488,12 +1589,44 @@ GDesc make_desc(const lexbfs_graph_t *g, char *ws, const SingleWs &L, int32_t *o
     d.failkey = (uint32_t *)(ws + L.failkey);
     d.gtab = (uint32_t *)(ws + L.gtab);
     d.res = res;
+    d.nnz = g->nnz;
     return d;
+}
+
+// Text of the first error bit of the input check.
+const char *egraph_text(uint32_t bad)
+{
+    if (bad & kBadRowPtr) return "row pointers are not non-decreasing from 0 to nnz";
+    if (bad & kBadId) return "a column index lies outside 0..n-1";
+    if (bad & kSelfLoop) return "a vertex is listed in its own row (self-loop)";
+    if (bad & kUnsorted) return "a CSR row is not strictly ascending (unsorted or duplicate entry)";
+    if (bad & kNotInBits) return "a CSR entry is missing from the bitset";
+    if (bad & kAsym) return "the adjacency is not symmetric";
+    if (bad & kExtraBits) return "the bitset holds entries the CSR lacks (or bits at or above n)";
+    return "graph violates the input contract";
+}
+
+// The input check of one graph, run to completion before returning (the
+// verdict is needed on the host): LEXBFS_OK or LEXBFS_EGRAPH. `status` is
+// one device word of the caller's workspace.
+int check_graph_single(const GDesc &d, uint32_t *status, hipStream_t s)
+{
+    if (d.n <= 0) return LEXBFS_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, status, 1, 0u);
+    const int blocks = std::max(1, std::min((d.n + 3) / 4, 2048));
+    hipLaunchKernelGGL(k_validate_one, dim3(blocks), dim3(kValidateThreads), 0, s, d, status);
+    LX_CHECK_LAUNCH("input check launch");
+    uint32_t h = 0;
+    hipError_t e = hipMemcpyAsync(&h, status, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "reading the input check");
+    if (h) return fail_code(LEXBFS_EGRAPH, egraph_text(h));
+    return LEXBFS_OK;
 }
 
 // Batch plan kept in the workspace.
 struct BatchWs {
-    size_t qctr, gds, sorted, failkeys, arrays, total;
+    size_t qctr, gds, sorted, failkeys, status, arrays, total;
 };
 
 // Largest n of the 256-lane tier (state in one workgroup's LDS).
@@ -1526,6 +1659,7 @@ BatchWs batch_layout(const lexbfs_graph_t *gs, int32_t count)
     L.gds = off; off += al(sizeof(GDesc) * (size_t)count);
     L.sorted = off; off += al(4 * (size_t)count);
     L.failkeys = off; off += al(4 * (size_t)count);
+    L.status = off; off += al(4 * (size_t)count);
     L.arrays = off; off += arrays;
     L.total = off;
     return L;
@@ -1760,6 +1894,16 @@ int lexbfs_order(const lexbfs_graph_t *g, int32_t *order, int32_t *rank, int32_t
     return launch_lexbfs_single(d, (hipStream_t)stream);
 }
 
+int lexbfs_validate(const lexbfs_graph_t *g, void *ws, size_t ws_bytes, void *stream)
+{
+    const int rc = validate_graph(g);
+    if (rc) return rc;
+    if (g->n == 0) return LEXBFS_OK;
+    if (!ws || ws_bytes < kAlign) return LEXBFS_ENOWS;
+    const GDesc d = make_desc(g, (char *)ws, single_layout(g->n), nullptr, nullptr, nullptr, nullptr, nullptr);
+    return check_graph_single(d, (uint32_t *)ws, (hipStream_t)stream);
+}
+
 int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_outputs_t *out, void *ws,
                  size_t ws_bytes, uint32_t flags, void *stream)
 {
@@ -1773,6 +1917,10 @@ int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_out
                               out ? out->parent : nullptr, out ? out->cycle : nullptr, res);
     if ((flags & LEXBFS_FLAG_PER_STEP) && (flags & LEXBFS_FLAG_MCS))
         return fail_code(LEXBFS_EINVAL, "the per-step form exists for LexBFS only");
+    if (flags & LEXBFS_FLAG_VALIDATE) {
+        rc = check_graph_single(d, (uint32_t *)((char *)ws + L.failkey + 64), s);
+        if (rc) return rc;
+    }
     if (g->n > 0) {
         rc = (flags & LEXBFS_FLAG_MCS)        ? launch_mcs_single(d, s)
              : (flags & LEXBFS_FLAG_PER_STEP) ? launch_lexbfs_per_step(d, s)
@@ -1807,6 +1955,31 @@ size_t lexbfs_batch_workspace_bytes(const lexbfs_graph_t *gs, int32_t count)
 }
 
 namespace {
+// The input check of every graph of a batch (descriptors already staged at
+// dg), run to completion: LEXBFS_OK or LEXBFS_EGRAPH naming the first bad
+// graph.
+int check_graphs_batch(const lexbfs_graph_t *gs, int32_t count, const GDesc *dg, uint32_t *status, hipStream_t s)
+{
+    int maxn = 0;
+    for (int i = 0; i < count; ++i) maxn = std::max(maxn, gs[i].n);
+    if (maxn == 0) return LEXBFS_OK;
+    const int bpg = std::max(1, std::min((maxn + 63) / 64, 16));  // blocks per graph
+    hipLaunchKernelGGL(k_fill_u32, dim3((count + 255) / 256), dim3(256), 0, s, status, count, 0u);
+    hipLaunchKernelGGL(k_validate_batch, dim3((unsigned)count * (unsigned)bpg), dim3(kValidateThreads), 0, s, dg,
+                       count, bpg, status);
+    LX_CHECK_LAUNCH("batch input check launch");
+    std::vector<uint32_t> h((size_t)count);
+    hipError_t e = hipMemcpyAsync(h.data(), status, 4 * (size_t)count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "reading the batch input check");
+    for (int i = 0; i < count; ++i)
+        if (h[i]) {
+            snprintf(t_last_error, sizeof t_last_error, "graph %d: %s", i, egraph_text(h[i]));
+            return LEXBFS_EGRAPH;
+        }
+    return LEXBFS_OK;
+}
+
 // interleave: graphs on wavefront and 256-lane teams break ties by the
 // interleaved rank (ilv_rank) instead of the id; plan->ilv_k records their K.
 int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs, lexbfs_result_t *res,
@@ -1909,6 +2082,7 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         }
         d.failkey = (uint32_t *)(w + L.failkeys) + i;
         d.res = res + i;
+        d.nnz = g.nnz;
         hsorted[i] = i;
     }
     auto tier = [&](int i) { return gs[i].n > tier_max ? 2 : gs[i].n > wave_max_n ? 0 : 1; };
@@ -1960,6 +2134,14 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
     if (e != hipSuccess) {
         delete P;
         return fail_hip(e, "staging the batch plan");
+    }
+    if (flags & LEXBFS_FLAG_VALIDATE) {
+        const int rc = check_graphs_batch(gs, count, (const GDesc *)(w + L.gds), (uint32_t *)(w + L.status),
+                                          (hipStream_t)stream);
+        if (rc) {
+            delete P;
+            return rc;
+        }
     }
     *plan_out = P;
     return LEXBFS_OK;

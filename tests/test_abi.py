@@ -180,3 +180,25 @@ def test_multi_sweep_argument_errors(lib):
     assert lib.unit_interval_test_batch(arr, 2, res, None, ws, bneed - 1, None) == _lib.LEXBFS_ENOWS
     arr = (_lib.lexbfs_graph_t * 2)(fake_graph(10), fake_graph(70000))
     assert lib.unit_interval_test_batch(arr, 2, res, None, ws, 1 << 40, None) == _lib.LEXBFS_ETOOBIG
+
+
+def test_validate_argument_errors(lib):
+    """lexbfs_validate rejects bad arguments before any device work; an
+    empty graph needs no check (and no workspace)."""
+    ws = 0x10000
+    assert lib.lexbfs_validate(None, ws, 256, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(-1)
+    assert lib.lexbfs_validate(ctypes.byref(g), ws, 256, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(_lib.LEXBFS_MAX_N + 1)
+    assert lib.lexbfs_validate(ctypes.byref(g), ws, 256, None) == _lib.LEXBFS_ETOOBIG
+    g = fake_graph(100, W=1)
+    assert lib.lexbfs_validate(ctypes.byref(g), ws, 256, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(100)
+    g.nnz = 1 << 31
+    assert lib.lexbfs_validate(ctypes.byref(g), ws, 256, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(100)
+    assert lib.lexbfs_validate(ctypes.byref(g), None, 256, None) == _lib.LEXBFS_ENOWS
+    assert lib.lexbfs_validate(ctypes.byref(g), ws, 255, None) == _lib.LEXBFS_ENOWS
+    g = fake_graph(0, nnz=0)
+    assert lib.lexbfs_validate(ctypes.byref(g), None, 0, None) == _lib.LEXBFS_OK
+    assert lib.lexbfs_strerror(_lib.LEXBFS_EGRAPH) == b"graph violates the input contract"

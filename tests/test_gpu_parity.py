@@ -189,8 +189,28 @@ def test_batch_workload_full():
     bad = []
     for i, (g, r) in enumerate(zip(graphs, rs)):
         ref = oracle.chordal_test(g)
-        if not (np.array_equal(r.order.cpu().numpy(), ref.order) and r.chordal == ref.chordal
-                and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()):
+        if not (np.array_equal(r.order.cpu().numpy(), ref.order) and np.array_equal(r.rank.cpu().numpy(), ref.rank)
+                and np.array_equal(r.parent.cpu().numpy(), ref.parent) and r.chordal == ref.chordal
+                and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist() and r.fallback == ref.fallback):
+            bad.append(i)
+    assert bad == []
+    assert sum(r.chordal for r in rs) == 2048
+
+
+def test_batch_workload_full_mcs():
+    """The whole 4,096-graph batch workload under LEXBFS_FLAG_MCS (the MCS
+    order of Section 5.1 and the same test, Theorem 5.2): order, rank,
+    parent, verdict, witness and certificate of every graph."""
+    graphs = gg.config_batch()
+    say(f"[parity] batch workload full MCS count={len(graphs)}")
+    dgs = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
+    rs = lx.chordal_test_batch(dgs, outputs=True, flags=lx.LEXBFS_FLAG_MCS)
+    bad = []
+    for i, (g, r) in enumerate(zip(graphs, rs)):
+        ref = oracle.chordal_test(g, "mcs")
+        if not (np.array_equal(r.order.cpu().numpy(), ref.order) and np.array_equal(r.rank.cpu().numpy(), ref.rank)
+                and np.array_equal(r.parent.cpu().numpy(), ref.parent) and r.chordal == ref.chordal
+                and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist() and r.fallback == ref.fallback):
             bad.append(i)
     assert bad == []
     assert sum(r.chordal for r in rs) == 2048

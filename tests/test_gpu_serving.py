@@ -87,3 +87,19 @@ def test_random_streams(seed):
     out = serving.serve(graphs, arr, budget_bytes=budget, outputs=True)
     check(out, graphs)
     assert out["peak_bytes"] <= budget
+
+
+def test_serving_stream_spans_the_serving_sizes():
+    """One stream whose sizes span the serving workload's whole range,
+    N log-uniform on [64, 32768] with both ends present, every response
+    checked against the oracle (order included)."""
+    graphs, arr = stream(40, 64, 32768, 11)
+    graphs.append(gg.mix_graph(64, 0, 0, gg.graph_seed(11, 5000)))
+    graphs.append(gg.mix_graph(32768, 2, 9, gg.graph_seed(11, 5001)))
+    graphs.append(gg.mix_graph(32768, 1, 0, gg.graph_seed(11, 5002)))
+    arr = np.append(arr * 2e-3, [arr[-1] * 2e-3 + 0.001 * k for k in range(1, 4)])
+    ns = sorted(g.n for g in graphs)
+    print(f"[serving] full-range stream: {len(graphs)} requests, N from {ns[0]} to {ns[-1]}", flush=True)
+    assert ns[0] == 64 and ns[-1] == 32768
+    out = serving.serve(graphs, arr, budget_bytes=64 << 30, outputs=True)
+    check(out, graphs)
