@@ -431,23 +431,26 @@ constexpr uint16_t kNoParent = 0xFFFFu;
 __host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // LDS of one graph's state. Tables in LDS:
-//   starts u64[wn] | red u32[2 waves] | cls u16[n] | clast u16[n] | cnt u32[n] | rem u16[n] (optional)
+//   starts u64[wn] | red u32[8 waves] | cls u16[n] | clast u16[n] | cnt u32[n] | rem u16[n] (optional)
 // Tables in global memory:
-//   starts u64[wn] | red u32[2 waves] | cls u16[n]
+//   starts u64[wn] | red u32[8 waves] | cls u16[n]
+// red: words [0, 4 waves) hold the two alternating reduction buffers, words
+// [4 waves, 5 waves) every wave's runner-up key of the last selection.
 // Every array starts on a 16-byte boundary (cls is read 16 bytes at a time).
+constexpr size_t kRedBytes = 32;  // LDS bytes of `red` per wavefront
 __host__ __device__ inline size_t lds_bytes_lds_tables(int n, int team, bool with_rem)
 {
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
     const size_t a = align_up(2 * (size_t)n, 16);
-    return align_up(8 * wn, 16) + align_up(16 * nred, 16) + 2 * a + align_up(4 * (size_t)n, 16) + (with_rem ? a : 0);
+    return align_up(8 * wn, 16) + kRedBytes * nred + 2 * a + align_up(4 * (size_t)n, 16) + (with_rem ? a : 0);
 }
 
 __host__ __device__ inline size_t lds_bytes_global_tables(int n, int team)
 {
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
-    return align_up(8 * wn, 16) + align_up(16 * nred, 16) + align_up(2 * (size_t)n, 16);
+    return align_up(8 * wn, 16) + kRedBytes * nred + align_up(2 * (size_t)n, 16);
 }
 
 template <bool kWithRem>
@@ -470,7 +473,7 @@ __device__ __forceinline__ LdsLayout<kWithRem> carve_lds(void *base, int n, int 
     L.starts = (uint64_t *)p;
     p += align_up(8 * wn, 16);
     L.red = (uint32_t *)p;
-    p += align_up(16 * nred, 16);
+    p += kRedBytes * nred;
     L.cls = (uint16_t *)p;
     L.tab.clast = (uint16_t *)(p + a);
     L.tab.cnt = (uint32_t *)(p + 2 * a);
@@ -516,7 +519,7 @@ __device__ __forceinline__ LdsLayoutG carve_lds_g(void *base, int n, int team)
     L.starts = (uint64_t *)p;
     p += align_up(8 * wn, 16);
     L.red = (uint32_t *)p;
-    p += align_up(16 * nred, 16);
+    p += kRedBytes * nred;
     L.cls = (uint16_t *)p;
     return L;
 }
@@ -608,6 +611,33 @@ __device__ __forceinline__ uint32_t pick_key_ilv(uint64_t top, uint64_t nb, int 
 }
 
 
+// Second-best selection key of one lane (0 if it has no second candidate):
+// the next member of the pivot-adjacent part of the top class, else the
+// first member of the rest of it. Same key format as pick_key.
+__device__ __forceinline__ uint32_t pick_key2(uint64_t top, uint64_t nb, uint32_t wbase)
+{
+    const uint64_t a = top & nb;
+    const uint64_t r = top & ~nb;
+    const uint64_t a2 = a & (a - 1ull);
+    if (a2) return 0x20000u | (0xFFFFu - (wbase + (uint32_t)ctz64(a2)));
+    const uint64_t c = a ? r : (r & (r - 1ull));
+    if (c) return 0x10000u | (0xFFFFu - (wbase + (uint32_t)ctz64(c)));
+    return 0u;
+}
+
+__device__ __forceinline__ uint32_t pick_key2_ilv(uint64_t top, uint64_t nb, int sh, uint32_t t, uint32_t tl,
+                                                  uint32_t cl)
+{
+    const uint64_t a = top & nb;
+    const uint64_t r = top & ~nb;
+    const uint64_t a2 = a & (a - 1ull);
+    if (a2) return 0x20000u | (0xFFFFu - ilv_rank((uint32_t)(ctz64(a2) - sh), t, tl, cl));
+    const uint64_t c = a ? r : (r & (r - 1ull));
+    if (c) return 0x10000u | (0xFFFFu - ilv_rank((uint32_t)(ctz64(c) - sh), t, tl, cl));
+    return 0u;
+}
+
+
 // ---------------------------------------------------------------------------
 // LexBFS on one graph by one team.
 //   row_ptr is read once (initial rem = degree) when the tables are in LDS.
@@ -656,7 +686,12 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     uint64_t cmask = (K == 64) ? ~0ull : (((1ull << K) - 1ull) << sh);
     if (wi == wn - 1 && (n & 63)) cmask &= (1ull << (n & 63)) - 1ull;
     const bool owner = vbase < n;
-    LX_GLOBAL const uint64_t *rowbase = bits + wi;
+    // Lanes past the last vertex read a word of the row as well (the last
+    // one), so that every row load is issued by every lane: a load skipped
+    // by part of the team would leave the compiler unsure how many loads are
+    // in flight, and every later wait would then wait for all of them.
+    LX_GLOBAL const uint64_t *rowbase = bits + min(wi, wn - 1);
+    const uint64_t omask = owner ? cmask : 0ull;  // my vertices (none past the last)
 
     for (int v = t; v < n; v += T) {
         cls[v] = 0;
@@ -678,9 +713,9 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     uint64_t top = um;                   // my members of the top class
     uint32_t x = 0;                      // first pivot: vertex 0 (smallest id, all labels empty)
     bool xrem = !kRem || rem[0] > 0;     // does the pivot still have unnumbered neighbours?
-    uint64_t rw = (owner && xrem) ? rowbase[0] : 0ull;  // my chunk's word of the pivot's row
-    uint32_t xp = kNoParent;  // the pivot's parent (kPeo)
-    uint64_t rp = 0ull;       // my chunk's word of the parent's row (kPeo)
+    uint64_t rw = rowbase[0];            // my chunk's word of the pivot's row
+    uint32_t xp = kNoParent;             // the pivot's parent (kPeo)
+    uint64_t rp = 0ull;                  // my chunk's word of the parent's row (kPeo)
     uint32_t xcls = 0;        // the pivot's (post-split) class, derived at selection
     int par = 0;
     int U = n;
@@ -691,6 +726,21 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     // order.)
     uint32_t eu = (kPeo || kIlv) ? 1u : (uint32_t)(row_ptr[n] >> 1);
     bool tail = false;
+    // Row prefetch. The pivot after next is almost always the runner-up of
+    // the current selection (the second-best key: the next member of the
+    // part of the top class adjacent to the pivot, else the first member of
+    // the rest of it). Its row is requested at the top of the next step, a
+    // phase A and a reduction before the team asks for it as the pivot row,
+    // so that request finds the row in L2 (or already on its way). The
+    // prefetched word is never used inside the loop, so no step waits for
+    // it: successive prefetches land in one register in issue order, and
+    // the last one is consumed after the loop. The load is a relaxed atomic
+    // so that it is neither dropped nor moved out of the loop (a plain load
+    // whose value only leaves the loop could be sunk past it).
+    uint32_t k2 = 0u;       // runner-up key of the last selection (wave teams)
+    bool k2_ok = false;     // is the runner-up of the last selection readable?
+    uint64_t pf = 0ull, pf2 = 0ull;  // the prefetched words (never read)
+    uint32_t *red2 = red + 4 * NW;  // every wave's runner-up key
     int i = 0;
     for (; i < n; ++i) {
         U -= 1;
@@ -722,22 +772,48 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             top &= ~(1ull << (x & 63));
         }
         uint64_t nb = rw & um;
-        uint64_t bad = 0ull;  // earlier neighbours of x outside N(p), p excluded
+        // Earlier neighbours of x in my chunk, p(x) excluded (kPeo): x fails
+        // if one of them is outside N(p(x)). Tested after phase A, so that
+        // the parent's row, requested after the pivot's, has time to arrive.
+        uint64_t lnb = 0ull;
         if (kPeo && xp != kNoParent) {
-            bad = rw & ~um & cmask & ~rp;
-            if ((xp >> 6) == (uint32_t)wi) bad &= ~(1ull << (xp & 63));
+            lnb = rw & ~um & omask;
+            if ((xp >> 6) == (uint32_t)wi) lnb &= ~(1ull << (xp & 63));
         }
         // Global stores only after the row word is in: on gfx9 the memory
         // counter covers stores too, so a store issued between the row load
         // and its use would hold up the use until the store completes. The
         // empty asm pins the use of the row here, ahead of the stores.
-        __asm__ volatile("" : "+v"(nb), "+v"(bad)::"memory");
-        if (kPeo && bad) atomicMin(fp.fk, (uint32_t)i);
+        __asm__ volatile("" : "+v"(nb), "+v"(lnb)::"memory");
+        {
+            // Issued on every step, by every lane (see rowbase); without a
+            // readable runner-up it asks for the current pivot's row again.
+            uint32_t g = k2;
+            if (NW > 1) {
+                g = red2[0];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) g = max(g, red2[w]);
+            }
+            g = k2_ok ? g : 0u;
+            const uint32_t gv =
+                g ? (kIlv ? ilv_id(0xFFFFu - (g & 0xFFFFu), tl, cl, (uint32_t)K) : 0xFFFFu - (g & 0xFFFFu)) : x;
+            const uint32_t gc = min(gv, (uint32_t)(n - 1));
+            pf = __hip_atomic_load(rowbase + (int64_t)gc * W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (kPeo) {  // and the row of its parent as it stands, for the fused test
+                const uint32_t pg = fp.par[gc];
+                pf2 = __hip_atomic_load(rowbase + (int64_t)(pg != kNoParent ? pg : gc) * W, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (t == 0) {
             if (!gone) tab.set_last(stop, (uint32_t)(U - 1));
             else atomicAnd((unsigned long long *)&starts[stop >> 6], ~(1ull << (stop & 63)));  // class gone
-            order[i] = (int32_t)x;
-            rank[x] = i;
+            if (kPeo) {
+                cls[x] = (uint16_t)i;  // numbered: its class id slot now keeps its rank
+            } else {
+                order[i] = (int32_t)x;
+                rank[x] = i;
+            }
         }
 
         // Phase A: count the neighbours of every hit class; record the parent.
@@ -760,6 +836,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
                 tab.inc(C);
             }
         }
+        if (kPeo && (lnb & ~rp)) atomicMin(fp.fk, (uint32_t)i);
         if (i + 1 == n) break;
 
         // Next pivot (see the header comment). The candidate class is the top
@@ -804,6 +881,11 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         const uint32_t key = kIlv ? pick_key_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key(top, nb, wbase);
         const uint32_t k = tm.max_sum_all(key, sums, red + par * 2 * NW);
         par ^= 1;
+        // This lane's best key once the winner is taken out (its own second
+        // key if it holds the winner); reduced over the wave after the row
+        // loads are issued.
+        const uint32_t key_ru =
+            key != k ? key : (kIlv ? pick_key2_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key2(top, nb, wbase));
         const uint32_t c_adj = sums & 0xFFFFu;
         if (!kPeo && !kIlv) {
             eu -= sums >> 16;
@@ -818,10 +900,16 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         // The next pivot's row first (the latency that bounds the step); a
         // pivot with no unnumbered neighbour may not need it, but asking rem
         // first would put an LDS round trip in front of the load.
-        const uint64_t rwn = owner ? rowbase[(int64_t)xn * W] : 0ull;
+        const uint64_t rwn = rowbase[(int64_t)xn * W];  // past the last vertex: masked by um
         const bool nrem = !kRem || rem[xn] > 0;
         const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
-        const uint64_t rpn = (kPeo && owner && pn != kNoParent) ? rowbase[(int64_t)pn * W] : 0ull;
+        const uint64_t rpn = kPeo ? rowbase[(int64_t)(pn != kNoParent ? pn : xn) * W] : 0ull;  // used if p exists
+        const uint32_t k2w = wave_max_dpp(key_ru);
+        if (NW > 1) {
+            if ((t & 63) == 0) red2[t >> 6] = k2w;  // read after barrier B
+        } else {
+            k2 = k2w;
+        }
 
         // Phase B: move the neighbours to the upper part of their class; the
         // last neighbour of a class to leave closes it.
@@ -869,6 +957,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             }
         }
         if (xrem) tm.sync();  // barrier B: nothing to order when the pivot split nothing
+        k2_ok = NW == 1 || xrem;
         x = xn;
         rw = rwn;
         rp = rpn;
@@ -930,13 +1019,18 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             if (sw) E = ((uint32_t)w << 6) | (uint32_t)ctz64(sw);
         }
     }
+    __asm__ volatile("" ::"v"(pf), "v"(pf2));
     if (kPeo) {
         tm.sync();
-        if (owner)
-            for (int v = vbase; v < min(vbase + K, n); ++v) {
-                const uint32_t p = fp.par[v];
-                parent[v] = p == kNoParent ? -1 : (int32_t)p;
-            }
+        // Outputs once per graph, from LDS: parents, and ranks from the class
+        // id slots of the numbered vertices.
+        for (int v = t; v < n; v += T) {
+            const uint32_t p = fp.par[v];
+            parent[v] = p == kNoParent ? -1 : (int32_t)p;
+            const int32_t r = (int32_t)cls[v];
+            rank[v] = r;
+            order[r] = (int32_t)v;
+        }
         if (t == 0) g_store(fp.failkey, *fp.fk);
     }
 }

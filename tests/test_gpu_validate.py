@@ -147,9 +147,10 @@ def test_valid_graphs_pass_and_results_match():
         assert np.array_equal(r.order.cpu().numpy(), ref.order)
         assert r.chordal == ref.chordal and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()
     batch = [lx.DeviceGraph.from_host(g, DEV) for g in graphs]
-    rs = lx.chordal_test_batch(batch, flags=lx.LEXBFS_FLAG_VALIDATE)
+    rs = lx.chordal_test_batch(batch, flags=lx.LEXBFS_FLAG_VALIDATE, outputs=True)
     for g, r in zip(graphs, rs):
         ref = oracle.chordal_test(g)
+        assert np.array_equal(r.order.cpu().numpy(), ref.order)
         assert r.chordal == ref.chordal and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()
 
 
