@@ -174,6 +174,32 @@ int lexbfs_order(const lexbfs_graph_t *g, int32_t *order, int32_t *rank, int32_t
 int chordal_test(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_outputs_t *out,
                  void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
+/*
+ * chordal_test_noalloc -- chordal_test for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the scratch lives in a fixed device
+ * array of the library instead of a caller workspace. Same arguments (minus
+ * ws), results and outputs as chordal_test. The caller still passes g, res
+ * and the optional outputs.
+ *   - The array holds chordal_test_noalloc_max_bytes() bytes (about
+ *     2.5 MiB), enough for every n up to LEXBFS_MAX_N. Each device the
+ *     library runs on holds its own copy until the process ends; the first
+ *     call on a device looks up that copy's address (a runtime query with
+ *     that device current, no allocation).
+ *   - All calls on one device share that device's array, which keeps the
+ *     last call's contents (each call writes what it reads before reading
+ *     it). Calls that overlap on one device (other streams or threads) race:
+ *     the caller serialises them.
+ *   - Allocates nothing and calls no allocating routine.
+ * Errors: as chordal_test, without LEXBFS_ENOWS; LEXBFS_ETOOBIG when the
+ * graph would need more scratch than the array holds; LEXBFS_EINVAL with
+ * LEXBFS_FLAG_VALIDATE (that check waits on the host: run lexbfs_validate,
+ * with a workspace, beforehand).
+ */
+size_t chordal_test_noalloc_max_bytes(void);
+int chordal_test_noalloc(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_outputs_t *out,
+                         uint32_t flags, void *stream);
+
 /* Schedule for chordal_test_batch. A graph with n <= wave_max_n is run by
  * one 64-lane wavefront; a larger one by a whole workgroup of
  * block_threads lanes. wave_max_n = 0 takes the built-in threshold (1024),

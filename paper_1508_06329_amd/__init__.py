@@ -112,6 +112,12 @@ class Result:
             return []
         return self.cycle[: self.cycle_len].tolist()
 
+    @classmethod
+    def from_record(cls, row: torch.Tensor, **outputs) -> "Result":
+        """Decode a result record (8 int32) that the library wrote."""
+        chordal, wit, clen, fb = _result_from(row.cpu())
+        return cls(chordal, wit, clen, fb, **outputs)
+
 
 class KernelTimer:
     """HIP-event timing of every library kernel launch while active.
@@ -320,6 +326,33 @@ def chordal_test(g: DeviceGraph, flags: int = 0, stream=None, outputs: bool = Tr
     _wait(stream)
     chordal, wit, clen, fb = _result_from(res.cpu())
     return Result(chordal, wit, clen, fb, **{k: v[:n] for k, v in tens.items()})
+
+
+def chordal_test_noalloc(g: DeviceGraph, res: torch.Tensor, outputs: Optional[dict] = None, flags: int = 0,
+                         stream=None) -> None:
+    """chordal_test with the library's fixed per-device scratch array instead
+    of a workspace: nothing is allocated on the call's path. The caller
+    passes the int32 result record `res` (8 entries, device) and optionally
+    int32 [n] device tensors keyed order, rank, parent and cycle; they are
+    valid once `stream` has reached the call (Result.from_record reads res).
+    Calls that overlap on one device share the array and race."""
+    lib = _lib.load()
+    outs = lexbfs_outputs_t()
+    tens = []
+    for k, v in (outputs or {}).items():
+        if k not in ("order", "rank", "parent", "cycle"):
+            raise ValueError(f"unknown output {k!r}")
+        setattr(outs, k, v.data_ptr())
+        tens.append(v)
+    d = g.desc()
+    rc = lib.chordal_test_noalloc(ctypes.byref(d), res.data_ptr(), ctypes.byref(outs), flags,
+                                  _stream_handle(stream))
+    _lib.check(rc, "chordal_test_noalloc")
+    _on_stream(stream, res, *tens)
+
+
+def chordal_test_noalloc_max_bytes() -> int:
+    return int(_lib.load().chordal_test_noalloc_max_bytes())
 
 
 def chordal_test_batch(graphs: Sequence[DeviceGraph], flags: int = 0, stream=None, outputs: bool = False,

@@ -35,7 +35,8 @@ EXPORTED = ["lexbfs_workspace_bytes", "lexbfs_validate", "lexbfs_order", "chorda
             "lexbfs_batch_plan_destroy", "lexbfs_strerror", "lexbfs_last_error", "lexbfs_profile_enable",
             "lexbfs_profile_collect", "lexbfs_batch_max_n", "lexbfs_build_bitset", "lexbfs_plus_workspace_bytes",
             "lexbfs_plus_order", "unit_interval_workspace_bytes", "unit_interval_test",
-            "unit_interval_batch_workspace_bytes", "unit_interval_test_batch", "lexbfs_abi_version"]
+            "unit_interval_batch_workspace_bytes", "unit_interval_test_batch", "lexbfs_abi_version",
+            "chordal_test_noalloc_max_bytes", "chordal_test_noalloc"]
 
 
 class lexbfs_graph_t(ctypes.Structure):
@@ -138,6 +139,10 @@ def load() -> ctypes.CDLL:
     lib.lexbfs_batch_max_n.argtypes = []
     lib.lexbfs_abi_version.restype = ctypes.c_int
     lib.lexbfs_abi_version.argtypes = []
+    lib.chordal_test_noalloc_max_bytes.restype = sz
+    lib.chordal_test_noalloc_max_bytes.argtypes = []
+    lib.chordal_test_noalloc.restype = ctypes.c_int
+    lib.chordal_test_noalloc.argtypes = [gp, vp, ctypes.POINTER(lexbfs_outputs_t), ctypes.c_uint32, vp]
     _lib = lib
     return lib
 

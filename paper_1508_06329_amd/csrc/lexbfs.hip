@@ -1296,7 +1296,7 @@ __global__ __launch_bounds__(kIbThreads) void k_ib_witness(const IDesc *__restri
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct DevInfo {
     int max_lds = 0;
@@ -1384,9 +1384,9 @@ struct SingleWs {
     size_t failkey, order, rank, parent, cycle, level, q0, q1, lnbuf, gtab, total;
 };
 
-SingleWs single_layout(int n)
+constexpr SingleWs single_layout(int n)
 {
-    SingleWs L;
+    SingleWs L{};
     const size_t a = al((size_t)(n > 0 ? n : 1) * 4);
     size_t off = 0;
     L.failkey = off; off += kAlign;
@@ -1401,6 +1401,38 @@ SingleWs single_layout(int n)
     L.gtab = off; off += 2 * a;
     L.total = off;
     return L;
+}
+
+// Scratch of chordal_test_noalloc: a single-graph workspace for the largest
+// supported n (about 2.5 MiB), one copy per device, held until the process
+// ends. Host code never names the array itself (on the host it is a
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the current device.
+constexpr size_t kScratchBytes = single_layout(LEXBFS_MAX_N).total;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+// The device address of this device's scratch array, looked up once per
+// device with that device current.
+int scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "querying the current device");
+    if (dev < 0 || dev >= 64) return fail_code(LEXBFS_EINVAL, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                   "looking up the scratch array's device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LEXBFS_OK;
 }
 
 // The LDS form the single-graph LexBFS kernel takes for n vertices on a
@@ -2466,6 +2498,26 @@ int32_t lexbfs_batch_max_n(void)
     const size_t lim = dynamic_lds_limit(k_batch<kBatchThreads, false>);
     if (!lim) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernel's LDS limit failed");
     return batch_tier_max_n(lim);
+}
+
+size_t chordal_test_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int chordal_test_noalloc(const lexbfs_graph_t *g, lexbfs_result_t *res, const lexbfs_outputs_t *out, uint32_t flags,
+                         void *stream)
+{
+    int rc = validate_graph(g);
+    if (rc) return rc;
+    if (!res) return LEXBFS_EINVAL;
+    if (flags & LEXBFS_FLAG_VALIDATE)
+        return fail_code(LEXBFS_EINVAL, "chordal_test_noalloc does not take LEXBFS_FLAG_VALIDATE (it waits on the host)");
+    const size_t need = single_layout(g->n).total;
+    if (need > kScratchBytes) return fail_code(LEXBFS_ETOOBIG, "graph needs more scratch than the fixed array holds");
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    // Every kernel of chordal_test sets the scratch it reads (failure key,
+    // tables, queues) before reading it, so nothing is cleared here.
+    return chordal_test(g, res, out, ws, kScratchBytes, flags, stream);
 }
 
 int chordal_test_batch(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t *outs,

@@ -116,6 +116,22 @@ def test_argument_errors(lib):
     lib.lexbfs_batch_plan_destroy(None)
 
 
+def test_noalloc_argument_errors(lib):
+    """The allocation-free entry point rejects bad arguments before any
+    device work, and its fixed scratch covers the largest supported graph."""
+    res = 0x20000
+    assert lib.chordal_test_noalloc_max_bytes() >= lib.lexbfs_workspace_bytes(_lib.LEXBFS_MAX_N)
+    assert lib.chordal_test_noalloc_max_bytes() < 8 << 20
+    assert lib.chordal_test_noalloc(None, res, None, 0, None) == _lib.LEXBFS_EINVAL
+    g = fake_graph(_lib.LEXBFS_MAX_N + 1)
+    assert lib.chordal_test_noalloc(ctypes.byref(g), res, None, 0, None) == _lib.LEXBFS_ETOOBIG
+    g = fake_graph(100)
+    assert lib.chordal_test_noalloc(ctypes.byref(g), None, None, 0, None) == _lib.LEXBFS_EINVAL
+    assert lib.chordal_test_noalloc(ctypes.byref(g), res, None, _lib.LEXBFS_FLAG_VALIDATE, None) == _lib.LEXBFS_EINVAL
+    g.reserved = 1
+    assert lib.chordal_test_noalloc(ctypes.byref(g), res, None, 0, None) == _lib.LEXBFS_EINVAL
+
+
 def test_workspace_sizes_grow(lib):
     sizes = [lib.lexbfs_workspace_bytes(n) for n in (0, 1, 64, 1000, 65536)]
     assert sizes == sorted(sizes) and sizes[0] > 0
