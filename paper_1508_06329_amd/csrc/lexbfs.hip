@@ -382,7 +382,7 @@ __device__ void finish_graph(const Team &tm, const GDesc &g, uint32_t flags, con
 // Kernels
 // ---------------------------------------------------------------------------
 // State placement of a single-graph LexBFS launch, most capable first.
-enum : int { kModeLdsRem = 0, kModeLds = 1, kModeCompact = 2, kModeGlobal = 3 };
+enum : int { kModeLds = 1, kModeCompact = 2, kModeGlobal = 3 };
 
 // kIlv: ties by the interleaved rank (the renamed graphs of LexBFS+ sweeps);
 // never used with the compact form.
@@ -396,16 +396,15 @@ __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
         lexbfs_team_compact(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_compact(lds, g.n, T));
     } else if (kMode == kModeGlobal) {
         LdsLayoutG L = carve_lds_g(lds, g.n, T);
-        GlobalTables tab{g.gtab, g.gtab + g.n};
+        GlobalTables tab(g.gtab, g.gtab + g.n);
         BlockTeam<T, true> tm{(int)threadIdx.x};
         lexbfs_team<BlockTeam<T, true>, GlobalTables, false, kIlv>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank,
-                                                                  g.parent, L.starts, L.cls, nullptr, tab, L.red);
+                                                                  g.parent, L.starts, L.cls, tab, L.red);
     } else {
-        constexpr bool kRem = kMode == kModeLdsRem;
-        LdsLayout<kRem> L = carve_lds<kRem>(lds, g.n, T);
+        LdsLayout L = carve_lds(lds, g.n, T);
         BlockTeam<T, false> tm{(int)threadIdx.x};
-        lexbfs_team<BlockTeam<T, false>, LdsTables<kRem>, false, kIlv, 32>(
-            tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, L.rem, L.tab, L.red);
+        lexbfs_team<BlockTeam<T, false>, LdsTables, false, kIlv, 32>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank,
+                                                                     g.parent, L.starts, L.cls, L.tab, L.red);
     }
 }
 
@@ -572,8 +571,8 @@ __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32
                              carve_mcs(region, g.n, Team::kSize, true, g.failkey));
     } else {
         BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
-        lexbfs_team<Team, LdsTables<true>, true, kIlv>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent,
-                                                        B.L.starts, B.L.cls, B.L.rem, B.L.tab, B.L.red, B.fp);
+        lexbfs_team<Team, LdsTables, true, kIlv>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent,
+                                                  B.L.starts, B.L.cls, B.L.tab, B.L.red, B.fp);
     }
     tm.sync_mem();  // order, rank, parent and the failing rank visible to the team
     if (!(flags & kFlagOrderOnly)) finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));
@@ -789,9 +788,9 @@ __global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__re
         lexbfs_team_compact(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_compact(lds, g.n, T));
     } else {
         LdsLayoutG L = carve_lds_g(lds, g.n, T);
-        GlobalTables tab{g.gtab, g.gtab + g.n};
+        GlobalTables tab(g.gtab, g.gtab + g.n);
         BlockTeam<T, true> tm{(int)threadIdx.x};
-        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, nullptr, tab, L.red);
+        lexbfs_team(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent, L.starts, L.cls, tab, L.red);
         tm.sync_mem();  // order and rank visible to every wave
         derive_parents(g.rp, g.ci, g.order, g.rank, g.parent, g.n, (int)(threadIdx.x >> 6), T / kWave);
     }
@@ -1436,19 +1435,16 @@ int scratch_address(void **out)
 }
 
 // The LDS form the single-graph LexBFS kernel takes for n vertices on a
-// T-lane team: the first of tables with rem, tables, compact, global tables
-// that fits.
+// T-lane team: the first of LDS tables, compact, global tables that fits.
 template <int T>
 int single_mode_T(int n, int &mode)
 {
-    const size_t lim_r = dynamic_lds_limit(k_lexbfs_single<T, kModeLdsRem>);
     const size_t lim_l = dynamic_lds_limit(k_lexbfs_single<T, kModeLds>);
     const size_t lim_c = dynamic_lds_limit(k_lexbfs_single<T, kModeCompact>);
     const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, kModeGlobal>);
-    if (!lim_r || !lim_l || !lim_c || !lim_g)
+    if (!lim_l || !lim_c || !lim_g)
         return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
-    if (lds_bytes_lds_tables(n, T, true) <= lim_r) mode = kModeLdsRem;
-    else if (lds_bytes_lds_tables(n, T, false) <= lim_l) mode = kModeLds;
+    if (lds_bytes_lds_tables(n, T) <= lim_l) mode = kModeLds;
     else if (lds_bytes_compact(n, T) <= lim_c) mode = kModeCompact;
     else if (lds_bytes_global_tables(n, T) <= lim_g) mode = kModeGlobal;
     else return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");
@@ -1475,10 +1471,8 @@ int launch_lexbfs_single_T(const GDesc &d, hipStream_t s, bool ilv)
     int rc = single_mode_T<T>(d.n, mode);
     if (rc) return rc;
     ProfScope ps(0, s);
-    if (mode == kModeLdsRem) {
-        rc = launch_single_mode<T, kModeLdsRem>(d, s, ilv, lds_bytes_lds_tables(d.n, T, true));
-    } else if (mode == kModeLds) {
-        rc = launch_single_mode<T, kModeLds>(d, s, ilv, lds_bytes_lds_tables(d.n, T, false));
+    if (mode == kModeLds) {
+        rc = launch_single_mode<T, kModeLds>(d, s, ilv, lds_bytes_lds_tables(d.n, T));
     } else if (mode == kModeCompact) {
         hipLaunchKernelGGL((k_lexbfs_single<T, kModeCompact>), dim3(1), dim3(T), lds_bytes_compact(d.n, T), s, d);
     } else {

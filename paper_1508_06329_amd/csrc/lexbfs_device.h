@@ -55,10 +55,10 @@
 // x_{i+1} is known as soon as x_i's row is in, and the load of x_{i+1}'s row
 // is issued before the splits of step i run.
 //
-// A pivot none of whose neighbours is still unnumbered causes no split; a
-// per-vertex count rem[v] of unnumbered neighbours (decremented during the
-// splits) lets the team skip loading such a pivot's row and the barrier
-// after the (empty) split phase.
+// A pivot none of whose neighbours is still unnumbered causes no split. The
+// selection's reduction also sums the pivot's unnumbered neighbours over the
+// team, so every lane knows it before the split phase and the team skips
+// the barrier after that (empty) phase.
 //
 // Closing a split class without a third barrier: every neighbour of class C
 // reads C's neighbour count and clast[C], then counts itself as moved with
@@ -371,14 +371,11 @@ struct BlockTeam {
 // (phase B). The low half is final and stable throughout phase B; the
 // neighbour that moves last (high half reaching the count) closes the class
 // and clears the word for the next step.
-// LDS form: clast 16-bit, optional rem; global form (large n): 32-bit
-// entries in L2, no rem.
+// LDS form: clast 16-bit; global form (large n): 32-bit entries in L2.
 // ---------------------------------------------------------------------------
-template <bool kWithRem>
 struct LdsTables {
     uint16_t *clast;
     uint32_t *cnt;
-    static constexpr bool kRem = kWithRem;
     static constexpr bool kInLds = true;
     __device__ __forceinline__ uint32_t last(uint32_t c) const { return clast[c]; }
     __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { clast[c] = (uint16_t)v; }
@@ -391,30 +388,39 @@ struct LdsTables {
     __device__ __forceinline__ uint32_t moved_by(uint32_t c, uint32_t k) const { return atomicAdd(&cnt[c], k << 16); }
 };
 
+// The global form is read and written by one workgroup only (its team), so
+// every access has workgroup scope: atomics complete in the L2 of the CU's
+// own die and loads may be served by the CU's L1, which the same CU's
+// atomics and stores keep current. (Agent scope would have to make each
+// access coherent across the dies of the device.)
 struct GlobalTables {
-    uint32_t *clast;
-    uint32_t *cnt;
-    static constexpr bool kRem = false;
+    LX_GLOBAL uint32_t *clast;
+    LX_GLOBAL uint32_t *cnt;
     static constexpr bool kInLds = false;
-    __device__ __forceinline__ uint32_t last(uint32_t c) const { return g_load(&clast[c]); }
-    __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { g_store(&clast[c], v); }
-    __device__ __forceinline__ uint32_t word(uint32_t c) const { return g_load(&cnt[c]); }
-    __device__ __forceinline__ void clear(uint32_t c) const { g_store(&cnt[c], 0u); }
-    __device__ __forceinline__ void inc(uint32_t c) const
+    static constexpr int kScope = __HIP_MEMORY_SCOPE_WORKGROUP;
+    __device__ GlobalTables(uint32_t *cl, uint32_t *ct) : clast(as_global(cl)), cnt(as_global(ct)) {}
+    __device__ __forceinline__ uint32_t last(uint32_t c) const
     {
-        __hip_atomic_fetch_add(&cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __hip_atomic_load(clast + c, __ATOMIC_RELAXED, kScope);
     }
+    __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const
+    {
+        __hip_atomic_store(clast + c, v, __ATOMIC_RELAXED, kScope);
+    }
+    __device__ __forceinline__ uint32_t word(uint32_t c) const { return __hip_atomic_load(cnt + c, __ATOMIC_RELAXED, kScope); }
+    __device__ __forceinline__ void clear(uint32_t c) const { __hip_atomic_store(cnt + c, 0u, __ATOMIC_RELAXED, kScope); }
+    __device__ __forceinline__ void inc(uint32_t c) const { __hip_atomic_fetch_add(cnt + c, 1u, __ATOMIC_RELAXED, kScope); }
     __device__ __forceinline__ void add(uint32_t c, uint32_t k) const
     {
-        __hip_atomic_fetch_add(&cnt[c], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(cnt + c, k, __ATOMIC_RELAXED, kScope);
     }
     __device__ __forceinline__ uint32_t moved(uint32_t c) const
     {
-        return __hip_atomic_fetch_add(&cnt[c], 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __hip_atomic_fetch_add(cnt + c, 0x10000u, __ATOMIC_RELAXED, kScope);
     }
     __device__ __forceinline__ uint32_t moved_by(uint32_t c, uint32_t k) const
     {
-        return __hip_atomic_fetch_add(&cnt[c], k << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __hip_atomic_fetch_add(cnt + c, k << 16, __ATOMIC_RELAXED, kScope);
     }
 };
 
@@ -431,73 +437,66 @@ constexpr uint16_t kNoParent = 0xFFFFu;
 __host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // LDS of one graph's state. Tables in LDS:
-//   starts u64[wn] | red u32[8 waves] | cls u16[n] | clast u16[n] | cnt u32[n] | rem u16[n] (optional)
+//   starts u64[wn] | red u32[2 waves] | cls u16[n] | clast u16[n] | cnt u32[n]
 // Tables in global memory:
-//   starts u64[wn] | red u32[8 waves] | cls u16[n]
-// red: words [0, 4 waves) hold the two alternating reduction buffers, words
-// [4 waves, 5 waves) every wave's runner-up key of the last selection.
+//   starts u64[wn] | red u32[2 waves] | cls u16[n]
 // Every array starts on a 16-byte boundary (cls is read 16 bytes at a time).
-constexpr size_t kRedBytes = 32;  // LDS bytes of `red` per wavefront
-__host__ __device__ inline size_t lds_bytes_lds_tables(int n, int team, bool with_rem)
+__host__ __device__ inline size_t lds_bytes_lds_tables(int n, int team)
 {
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
     const size_t a = align_up(2 * (size_t)n, 16);
-    return align_up(8 * wn, 16) + kRedBytes * nred + 2 * a + align_up(4 * (size_t)n, 16) + (with_rem ? a : 0);
+    return align_up(8 * wn, 16) + align_up(16 * nred, 16) + 2 * a + align_up(4 * (size_t)n, 16);
 }
 
 __host__ __device__ inline size_t lds_bytes_global_tables(int n, int team)
 {
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
-    return align_up(8 * wn, 16) + kRedBytes * nred + align_up(2 * (size_t)n, 16);
+    return align_up(8 * wn, 16) + align_up(16 * nred, 16) + align_up(2 * (size_t)n, 16);
 }
 
-template <bool kWithRem>
 struct LdsLayout {
     uint64_t *starts;
     uint32_t *red;
     uint16_t *cls;
-    uint16_t *rem;
-    LdsTables<kWithRem> tab;
+    LdsTables tab;
 };
 
-template <bool kWithRem>
-__device__ __forceinline__ LdsLayout<kWithRem> carve_lds(void *base, int n, int team)
+__device__ __forceinline__ LdsLayout carve_lds(void *base, int n, int team)
 {
     const size_t wn = (size_t)(n + 63) / 64;
     const size_t nred = (size_t)(team / kWave > 0 ? team / kWave : 1);
     const size_t a = align_up(2 * (size_t)n, 16);
     char *p = (char *)base;
-    LdsLayout<kWithRem> L;
+    LdsLayout L;
     L.starts = (uint64_t *)p;
     p += align_up(8 * wn, 16);
     L.red = (uint32_t *)p;
-    p += kRedBytes * nred;
+    p += align_up(16 * nred, 16);
     L.cls = (uint16_t *)p;
     L.tab.clast = (uint16_t *)(p + a);
     L.tab.cnt = (uint32_t *)(p + 2 * a);
-    L.rem = kWithRem ? (uint16_t *)(p + 2 * a + align_up(4 * (size_t)n, 16)) : nullptr;
     return L;
 }
 
-// Batch graph state: the LDS tables with rem, then the parents and the
-// failing-rank word of the fused elimination test.
+// Batch graph state: the LDS tables, then the parents and the failing-rank
+// word of the fused elimination test.
 __host__ __device__ inline size_t lds_bytes_batch(int n, int team)
 {
-    return lds_bytes_lds_tables(n, team, true) + align_up(2 * (size_t)n, 16) + 16;
+    return lds_bytes_lds_tables(n, team) + align_up(2 * (size_t)n, 16) + 16;
 }
 
 struct BatchLayout {
-    LdsLayout<true> L;
+    LdsLayout L;
     FusedPeo fp;
 };
 
 __device__ __forceinline__ BatchLayout carve_batch(void *base, int n, int team, uint32_t *failkey)
 {
     BatchLayout B;
-    B.L = carve_lds<true>(base, n, team);
-    char *p = (char *)base + lds_bytes_lds_tables(n, team, true);
+    B.L = carve_lds(base, n, team);
+    char *p = (char *)base + lds_bytes_lds_tables(n, team);
     B.fp.par = (uint16_t *)p;
     B.fp.fk = (uint32_t *)(p + align_up(2 * (size_t)n, 16));
     B.fp.failkey = failkey;
@@ -519,7 +518,7 @@ __device__ __forceinline__ LdsLayoutG carve_lds_g(void *base, int n, int team)
     L.starts = (uint64_t *)p;
     p += align_up(8 * wn, 16);
     L.red = (uint32_t *)p;
-    p += kRedBytes * nred;
+    p += align_up(16 * nred, 16);
     L.cls = (uint16_t *)p;
     return L;
 }
@@ -611,36 +610,9 @@ __device__ __forceinline__ uint32_t pick_key_ilv(uint64_t top, uint64_t nb, int 
 }
 
 
-// Second-best selection key of one lane (0 if it has no second candidate):
-// the next member of the pivot-adjacent part of the top class, else the
-// first member of the rest of it. Same key format as pick_key.
-__device__ __forceinline__ uint32_t pick_key2(uint64_t top, uint64_t nb, uint32_t wbase)
-{
-    const uint64_t a = top & nb;
-    const uint64_t r = top & ~nb;
-    const uint64_t a2 = a & (a - 1ull);
-    if (a2) return 0x20000u | (0xFFFFu - (wbase + (uint32_t)ctz64(a2)));
-    const uint64_t c = a ? r : (r & (r - 1ull));
-    if (c) return 0x10000u | (0xFFFFu - (wbase + (uint32_t)ctz64(c)));
-    return 0u;
-}
-
-__device__ __forceinline__ uint32_t pick_key2_ilv(uint64_t top, uint64_t nb, int sh, uint32_t t, uint32_t tl,
-                                                  uint32_t cl)
-{
-    const uint64_t a = top & nb;
-    const uint64_t r = top & ~nb;
-    const uint64_t a2 = a & (a - 1ull);
-    if (a2) return 0x20000u | (0xFFFFu - ilv_rank((uint32_t)(ctz64(a2) - sh), t, tl, cl));
-    const uint64_t c = a ? r : (r & (r - 1ull));
-    if (c) return 0x10000u | (0xFFFFu - ilv_rank((uint32_t)(ctz64(c) - sh), t, tl, cl));
-    return 0u;
-}
-
-
 // ---------------------------------------------------------------------------
 // LexBFS on one graph by one team.
-//   row_ptr is read once (initial rem = degree) when the tables are in LDS.
+//   row_ptr: only row_ptr[n] (twice the edge count) is read, by single graphs.
 //   red: 2 * waves LDS words (alternating between consecutive reductions).
 //
 // kPeo fuses the perfect-elimination test of Section 5.2 into the steps:
@@ -657,7 +629,7 @@ __device__ __forceinline__ uint32_t pick_key2_ilv(uint64_t top, uint64_t nb, int
 template <class Team, class Tabs, bool kPeo = false, bool kIlv = false, int kPre = 16>
 __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
                             int32_t *order_, int32_t *rank_, int32_t *parent_, uint64_t *starts, uint16_t *cls,
-                            uint16_t *rem, const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{})
+                            const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{})
 {
     LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
     LX_GLOBAL const int32_t *__restrict__ row_ptr = as_global(row_ptr_);
@@ -666,7 +638,6 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     LX_GLOBAL int32_t *__restrict__ parent = as_global(parent_);
     constexpr int T = Team::kSize;
     constexpr int NW = Team::kWaves;
-    constexpr bool kRem = Tabs::kRem;
     // Class tables in L2: each lane handles its neighbours class by class,
     // one atomic round trip per class instead of one per neighbour, and the
     // parents are not written during the steps (a lane may own 64 neighbours
@@ -696,7 +667,6 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     for (int v = t; v < n; v += T) {
         cls[v] = 0;
         tab.clear(v);
-        if (kRem) rem[v] = (uint16_t)(row_ptr[v + 1] - row_ptr[v]);
         if (kPeo) fp.par[v] = kNoParent;
     }
     for (int w = t; w < wn; w += T) starts[w] = w == 0 ? 1ull : 0ull;  // one class, starting at 0
@@ -712,7 +682,6 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     uint64_t um = owner ? cmask : 0ull;  // my unnumbered vertices (word positions)
     uint64_t top = um;                   // my members of the top class
     uint32_t x = 0;                      // first pivot: vertex 0 (smallest id, all labels empty)
-    bool xrem = !kRem || rem[0] > 0;     // does the pivot still have unnumbered neighbours?
     uint64_t rw = rowbase[0];            // my chunk's word of the pivot's row
     uint32_t xp = kNoParent;             // the pivot's parent (kPeo)
     uint64_t rp = 0ull;                  // my chunk's word of the parent's row (kPeo)
@@ -726,21 +695,6 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
     // order.)
     uint32_t eu = (kPeo || kIlv) ? 1u : (uint32_t)(row_ptr[n] >> 1);
     bool tail = false;
-    // Row prefetch. The pivot after next is almost always the runner-up of
-    // the current selection (the second-best key: the next member of the
-    // part of the top class adjacent to the pivot, else the first member of
-    // the rest of it). Its row is requested at the top of the next step, a
-    // phase A and a reduction before the team asks for it as the pivot row,
-    // so that request finds the row in L2 (or already on its way). The
-    // prefetched word is never used inside the loop, so no step waits for
-    // it: successive prefetches land in one register in issue order, and
-    // the last one is consumed after the loop. The load is a relaxed atomic
-    // so that it is neither dropped nor moved out of the loop (a plain load
-    // whose value only leaves the loop could be sunk past it).
-    uint32_t k2 = 0u;       // runner-up key of the last selection (wave teams)
-    bool k2_ok = false;     // is the runner-up of the last selection readable?
-    uint64_t pf = 0ull, pf2 = 0ull;  // the prefetched words (never read)
-    uint32_t *red2 = red + 4 * NW;  // every wave's runner-up key
     int i = 0;
     for (; i < n; ++i) {
         U -= 1;
@@ -772,39 +726,19 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             top &= ~(1ull << (x & 63));
         }
         uint64_t nb = rw & um;
-        // Earlier neighbours of x in my chunk, p(x) excluded (kPeo): x fails
-        // if one of them is outside N(p(x)). Tested after phase A, so that
-        // the parent's row, requested after the pivot's, has time to arrive.
-        uint64_t lnb = 0ull;
+        // Earlier neighbours of x in my chunk outside N(p(x)), p(x) itself
+        // excluded (kPeo): x fails if there is one.
+        uint64_t bad = 0ull;
         if (kPeo && xp != kNoParent) {
-            lnb = rw & ~um & omask;
-            if ((xp >> 6) == (uint32_t)wi) lnb &= ~(1ull << (xp & 63));
+            bad = rw & ~um & omask & ~rp;
+            if ((xp >> 6) == (uint32_t)wi) bad &= ~(1ull << (xp & 63));
         }
         // Global stores only after the row word is in: on gfx9 the memory
         // counter covers stores too, so a store issued between the row load
         // and its use would hold up the use until the store completes. The
         // empty asm pins the use of the row here, ahead of the stores.
-        __asm__ volatile("" : "+v"(nb), "+v"(lnb)::"memory");
-        {
-            // Issued on every step, by every lane (see rowbase); without a
-            // readable runner-up it asks for the current pivot's row again.
-            uint32_t g = k2;
-            if (NW > 1) {
-                g = red2[0];
-#pragma unroll
-                for (int w = 1; w < NW; ++w) g = max(g, red2[w]);
-            }
-            g = k2_ok ? g : 0u;
-            const uint32_t gv =
-                g ? (kIlv ? ilv_id(0xFFFFu - (g & 0xFFFFu), tl, cl, (uint32_t)K) : 0xFFFFu - (g & 0xFFFFu)) : x;
-            const uint32_t gc = min(gv, (uint32_t)(n - 1));
-            pf = __hip_atomic_load(rowbase + (int64_t)gc * W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (kPeo) {  // and the row of its parent as it stands, for the fused test
-                const uint32_t pg = fp.par[gc];
-                pf2 = __hip_atomic_load(rowbase + (int64_t)(pg != kNoParent ? pg : gc) * W, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
+        __asm__ volatile("" : "+v"(nb), "+v"(bad)::"memory");
+        if (kPeo && bad) atomicMin(fp.fk, (uint32_t)i);
         if (t == 0) {
             if (!gone) tab.set_last(stop, (uint32_t)(U - 1));
             else atomicAnd((unsigned long long *)&starts[stop >> 6], ~(1ull << (stop & 63)));  // class gone
@@ -817,27 +751,33 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         }
 
         // Phase A: count the neighbours of every hit class; record the parent.
+        // A team of several waves runs it before the selection, whose
+        // barrier then also separates it from phase B. One wavefront needs
+        // no barrier (its LDS operations complete in order), so it selects
+        // the next pivot first and issues that row's load before phase A:
+        // the load then overlaps both phases.
         uint32_t C0 = 0;  // class of my first neighbour, reused in phase B
-        if (kGroup) {
-            for (uint64_t m = nb; m;) {
-                const uint32_t C = cls[(int)wbase + ctz64(m)];
-                const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
-                tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
-                m &= ~g;
+        auto phase_a = [&]() {
+            if (kGroup) {
+                for (uint64_t m = nb; m;) {
+                    const uint32_t C = cls[(int)wbase + ctz64(m)];
+                    const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
+                    tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
+                    m &= ~g;
+                }
+            } else {
+                for (uint64_t m = nb; m; m &= m - 1) {
+                    const int y = (int)wbase + ctz64(m);
+                    const uint32_t C = cls[y];
+                    if (m == nb) C0 = C;
+                    if (kPeo) fp.par[y] = (uint16_t)x;
+                    else parent[y] = (int32_t)x;
+                    tab.inc(C);
+                }
             }
-        } else {
-            for (uint64_t m = nb; m; m &= m - 1) {
-                const int y = (int)wbase + ctz64(m);
-                const uint32_t C = cls[y];
-                if (m == nb) C0 = C;
-                if (kPeo) fp.par[y] = (uint16_t)x;
-                else parent[y] = (int32_t)x;
-                if (kRem) rem[y] = (uint16_t)(rem[y] - 1);
-                tab.inc(C);
-            }
-        }
-        if (kPeo && (lnb & ~rp)) atomicMin(fp.fk, (uint32_t)i);
-        if (i + 1 == n) break;
+        };
+        if (NW > 1) phase_a();
+        if (i + 1 == n) break;  // (the last pivot has no unnumbered neighbour)
 
         // Next pivot (see the header comment). The candidate class is the top
         // class, or -- when x emptied it -- the class directly below, i.e.
@@ -881,12 +821,8 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         const uint32_t key = kIlv ? pick_key_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key(top, nb, wbase);
         const uint32_t k = tm.max_sum_all(key, sums, red + par * 2 * NW);
         par ^= 1;
-        // This lane's best key once the winner is taken out (its own second
-        // key if it holds the winner); reduced over the wave after the row
-        // loads are issued.
-        const uint32_t key_ru =
-            key != k ? key : (kIlv ? pick_key2_ilv(top, nb, sh, (uint32_t)t, tl, cl) : pick_key2(top, nb, wbase));
         const uint32_t c_adj = sums & 0xFFFFu;
+        const bool xrem = (sums >> 16) != 0u;  // x has unnumbered neighbours: phase B has work
         if (!kPeo && !kIlv) {
             eu -= sums >> 16;
             tail = eu == 0u;
@@ -897,19 +833,13 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         // The candidate class spans [cand, U - 1]; its c_adj members adjacent
         // to x move to [U - c_adj, U - 1] and hold the next pivot.
         xcls = adj ? (uint32_t)U - c_adj : cand;
-        // The next pivot's row first (the latency that bounds the step); a
-        // pivot with no unnumbered neighbour may not need it, but asking rem
-        // first would put an LDS round trip in front of the load.
+        // The next pivot's row first: the latency that bounds the step.
         const uint64_t rwn = rowbase[(int64_t)xn * W];  // past the last vertex: masked by um
-        const bool nrem = !kRem || rem[xn] > 0;
-        const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
+        // The next pivot's parent: x when it is one of x's neighbours (its
+        // parent entry may not be written yet), else unchanged by this step.
+        const uint32_t pn = kPeo ? (adj ? x : (uint32_t)fp.par[xn]) : kNoParent;
         const uint64_t rpn = kPeo ? rowbase[(int64_t)(pn != kNoParent ? pn : xn) * W] : 0ull;  // used if p exists
-        const uint32_t k2w = wave_max_dpp(key_ru);
-        if (NW > 1) {
-            if ((t & 63) == 0) red2[t >> 6] = k2w;  // read after barrier B
-        } else {
-            k2 = k2w;
-        }
+        if (NW == 1) phase_a();
 
         // Phase B: move the neighbours to the upper part of their class; the
         // last neighbour of a class to leave closes it.
@@ -957,12 +887,10 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             }
         }
         if (xrem) tm.sync();  // barrier B: nothing to order when the pivot split nothing
-        k2_ok = NW == 1 || xrem;
         x = xn;
         rw = rwn;
         rp = rpn;
         xp = pn;
-        xrem = nrem;
         if (tail) {
             ++i;
             break;
@@ -1019,7 +947,6 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             if (sw) E = ((uint32_t)w << 6) | (uint32_t)ctz64(sw);
         }
     }
-    __asm__ volatile("" ::"v"(pf), "v"(pf2));
     if (kPeo) {
         tm.sync();
         // Outputs once per graph, from LDS: parents, and ranks from the class
