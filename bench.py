@@ -850,9 +850,10 @@ def bench_serving(args):
         log(f"{name}: offered {lam:.0f}/s -> {out['throughput']:.0f} tests/s, p50 {out['p50_ms']:.2f} ms, "
             f"p99 {out['p99_ms']:.2f} ms")
 
+    # Both servers get the same request stream (graphs and gaps) at each load.
     for frac in (0.5, 0.8):
-        run(f"per_graph@{frac}x", frac, min(R, 300), True)
-        run(f"batched@{frac}x", frac, min(R, 600), False)
+        run(f"per_graph@{frac}x", frac, R, True)
+        run(f"batched@{frac}x", frac, R, False)
     for mult in (4, 16, 64):
         run(f"batched@{mult}x", mult, R, False)
     sustained = [r["throughput"] for k, r in rows.items() if k.startswith("batched") and

@@ -766,23 +766,29 @@ __global__ void k_batch_init(const GDesc *__restrict__ gds, int count, uint32_t 
     }
 }
 
-// Batch graphs too large for a 256-lane team: one 1024-lane workgroup per
-// graph, with the state of a single-graph call (compact LDS layout when it
-// fits `lds_limit`, else class tables in global memory), then the graph's
-// sweep and certificate on the same workgroup.
+// Batch graphs too large for a 256-lane team: one workgroup per graph with
+// the team size and state of a single-graph call -- 512 lanes up to
+// kLargeMidMaxN vertices, 1,024 above; class tables in LDS when they fit
+// `lds_limit`, else the compact LDS layout, else class tables in global
+// memory -- then the graph's sweep and certificate on the same workgroup.
 constexpr int kLargeThreads = 1024;
+constexpr int kLargeMidThreads = 512;
+constexpr int kLargeMidMaxN = 32768;
 
-template <bool kMcs>
-__global__ __launch_bounds__(kLargeThreads) void k_batch_large(const GDesc *__restrict__ gds,
-                                                               const int32_t *__restrict__ which, uint32_t flags,
-                                                               int lds_limit)
+template <int T, bool kMcs>
+__global__ __launch_bounds__(T) void k_batch_large(const GDesc *__restrict__ gds, const int32_t *__restrict__ which,
+                                                   uint32_t flags, int lds_limit)
 {
     extern __shared__ uint64_t lds[];
-    constexpr int T = kLargeThreads;
     const GDesc g = gds[which[blockIdx.x]];
     if (kMcs) {
         BlockTeam<T, false> tm{(int)threadIdx.x};
         mcs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_mcs(lds, g.n, T, false, nullptr));
+    } else if (lds_bytes_lds_tables(g.n, T) <= (size_t)lds_limit) {
+        LdsLayout L = carve_lds(lds, g.n, T);
+        BlockTeam<T, false> tm{(int)threadIdx.x};
+        lexbfs_team<BlockTeam<T, false>, LdsTables, false, false, 32>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank,
+                                                                     g.parent, L.starts, L.cls, L.tab, L.red);
     } else if (lds_bytes_compact(g.n, T) <= (size_t)lds_limit) {
         BlockTeam<T, false> tm{(int)threadIdx.x};
         lexbfs_team_compact(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_compact(lds, g.n, T));
@@ -1828,21 +1834,26 @@ struct lexbfs_batch_plan {
     std::vector<char> table;
     int nbig = 0;    // graphs on 256-lane workgroup teams
     int nsmall = 0;  // graphs on wavefront teams
-    int nlarge = 0;  // graphs on 1024-lane workgroups (side stream)
+    int nlarge = 0;  // graphs on the large tier (side streams): 1024-lane workgroups first, then 512-lane ones
+    int nlarge_mid = 0;  // of which on 512-lane workgroups
     std::vector<int32_t> ilv_k;  // per graph: K of its team when its ties use the interleaved order, else 0
     bool interleaved = false;    // launch the interleaved-tie batch kernel
     size_t lds = 0;
-    size_t lds_large = 0;
+    size_t lds_large = 0;      // dynamic LDS of the 1024-lane kernel
+    size_t lds_large_mid = 0;  // and of the 512-lane kernel
     int region = 0;
     int blocks = 1;
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;  // side2: the 512-lane kernel when both sizes run
+    hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
     ~lexbfs_batch_plan()
     {
         if (side) (void)hipStreamSynchronize(side);
+        if (side2) (void)hipStreamSynchronize(side2);
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
+        if (join2) (void)hipEventDestroy(join2);
         if (side) (void)hipStreamDestroy(side);
+        if (side2) (void)hipStreamDestroy(side2);
     }
 };
 
@@ -2036,8 +2047,12 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
     }
     const bool mcs = (flags & LEXBFS_FLAG_MCS) != 0;
     const size_t maxl = mcs ? dynamic_lds_limit(k_batch<BT, true>) : dynamic_lds_limit(k_batch<BT, false>);
-    const size_t maxl_large = mcs ? dynamic_lds_limit(k_batch_large<true>) : dynamic_lds_limit(k_batch_large<false>);
-    if (!maxl || !maxl_large) return fail_code(LEXBFS_EHIP, "querying or raising the batch kernels' LDS limits failed");
+    const size_t maxl_large = mcs ? dynamic_lds_limit(k_batch_large<kLargeThreads, true>)
+                                  : dynamic_lds_limit(k_batch_large<kLargeThreads, false>);
+    const size_t maxl_mid = mcs ? dynamic_lds_limit(k_batch_large<kLargeMidThreads, true>)
+                                : dynamic_lds_limit(k_batch_large<kLargeMidThreads, false>);
+    if (!maxl || !maxl_large || !maxl_mid)
+        return fail_code(LEXBFS_EHIP, "querying or raising the batch kernels' LDS limits failed");
     const int tier_max = batch_tier_max_n(maxl);
     wave_max_n = std::min(wave_max_n, 64 * kWave);  // one lane owns at most 64 vertices
     // Every wave of a workgroup needs its own region: keep the wave
@@ -2047,8 +2062,13 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
     for (int i = 0; i < count; ++i) {
         const int n = gs[i].n;
         if (n > tier_max) {
-            if (lds_bytes_compact(n, kLargeThreads) > maxl_large && lds_bytes_global_tables(n, kLargeThreads) > maxl_large)
+            const int T = n <= kLargeMidMaxN ? kLargeMidThreads : kLargeThreads;
+            const size_t lim = n <= kLargeMidMaxN ? maxl_mid : maxl_large;
+            if (!mcs && lds_bytes_lds_tables(n, T) > lim && lds_bytes_compact(n, T) > lim &&
+                lds_bytes_global_tables(n, T) > lim)
                 return fail_code(LEXBFS_ETOOBIG, "a batch graph's state does not fit the workgroup LDS");
+            if (mcs && lds_bytes_mcs(n, T, false) > lim)
+                return fail_code(LEXBFS_ETOOBIG, "a batch graph's MCS state does not fit the workgroup LDS");
         } else if (n > wave_max_n) {
             maxn_block = std::max(maxn_block, n);
         } else {
@@ -2136,8 +2156,10 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
     P->nbig = nbig;
     P->nsmall = nsmall;
     P->nlarge = count - nbig - nsmall;
+    for (int k = nbig + nsmall; k < count; ++k) P->nlarge_mid += gs[hsorted[k]].n <= kLargeMidMaxN;
     P->lds = lds;
     P->lds_large = maxl_large;
+    P->lds_large_mid = maxl_mid;
     P->region = (int)region;
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -2145,14 +2167,18 @@ int plan_create(const lexbfs_graph_t *gs, int32_t count, const lexbfs_outputs_t 
         cus = 256;
     const int per_cu = std::max(1, (int)((size_t)device_max_lds() / lds));
     P->blocks = std::max(1, std::min(cus * per_cu, std::max(nbig, (nsmall + 3) / 4)));
-    if (P->nlarge > 0 && nbig + nsmall > 0 && side_stream) {
-        // The 1024-lane tier runs on a stream of the plan, forked from and
-        // joined back into the caller's stream at every launch.
+    const bool both_large = P->nlarge_mid > 0 && P->nlarge_mid < P->nlarge;
+    if (P->nlarge > 0 && (nbig + nsmall > 0 || both_large) && side_stream) {
+        // The large tier runs on streams of the plan (one per team size),
+        // forked from and joined back into the caller's stream at every
+        // launch.
         if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess ||
+            (both_large && (hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking) != hipSuccess ||
+                            hipEventCreateWithFlags(&P->join2, hipEventDisableTiming) != hipSuccess))) {
             delete P;
-            return fail_code(LEXBFS_EHIP, "creating the batch plan's stream and events");
+            return fail_code(LEXBFS_EHIP, "creating the batch plan's streams and events");
         }
     }
     const hipError_t e =
@@ -2338,26 +2364,46 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
     }
     LX_CHECK_LAUNCH("batch init launch");
     if (P->nlarge > 0) {
-        hipStream_t ls = s;
+        // 1024-lane graphs (n above kLargeMidMaxN) come first in `sorted`,
+        // then 512-lane ones; each size has its own kernel and, when both
+        // run, its own stream.
+        const int nl_big = P->nlarge - P->nlarge_mid;
+        const int32_t *first = sorted + P->nbig + P->nsmall;
+        hipStream_t ls = s, ls_mid = s;
         if (P->side) {
             hipError_t e = hipEventRecord(P->fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(P->side, P->fork, 0);
-            if (e != hipSuccess) return fail_hip(e, "forking the large-graph stream");
+            if (e == hipSuccess && P->side2) e = hipStreamWaitEvent(P->side2, P->fork, 0);
+            if (e != hipSuccess) return fail_hip(e, "forking the large-graph streams");
             ls = P->side;
+            ls_mid = P->side2 ? P->side2 : P->side;
         }
-        {
+        const bool mcs = (P->flags & LEXBFS_FLAG_MCS) != 0;
+        if (nl_big > 0) {
             ProfScope ps(0, ls);
-            if (P->flags & LEXBFS_FLAG_MCS)
-                hipLaunchKernelGGL(k_batch_large<true>, dim3(P->nlarge), dim3(kLargeThreads), P->lds_large, ls, dg,
-                                   sorted + P->nbig + P->nsmall, P->flags, (int)P->lds_large);
+            if (mcs)
+                hipLaunchKernelGGL((k_batch_large<kLargeThreads, true>), dim3(nl_big), dim3(kLargeThreads),
+                                   P->lds_large, ls, dg, first, P->flags, (int)P->lds_large);
             else
-                hipLaunchKernelGGL(k_batch_large<false>, dim3(P->nlarge), dim3(kLargeThreads), P->lds_large, ls, dg,
-                                   sorted + P->nbig + P->nsmall, P->flags, (int)P->lds_large);
+                hipLaunchKernelGGL((k_batch_large<kLargeThreads, false>), dim3(nl_big), dim3(kLargeThreads),
+                                   P->lds_large, ls, dg, first, P->flags, (int)P->lds_large);
+        }
+        if (P->nlarge_mid > 0) {
+            ProfScope ps(0, ls_mid);
+            if (mcs)
+                hipLaunchKernelGGL((k_batch_large<kLargeMidThreads, true>), dim3(P->nlarge_mid),
+                                   dim3(kLargeMidThreads), P->lds_large_mid, ls_mid, dg, first + nl_big, P->flags,
+                                   (int)P->lds_large_mid);
+            else
+                hipLaunchKernelGGL((k_batch_large<kLargeMidThreads, false>), dim3(P->nlarge_mid),
+                                   dim3(kLargeMidThreads), P->lds_large_mid, ls_mid, dg, first + nl_big, P->flags,
+                                   (int)P->lds_large_mid);
         }
         LX_CHECK_LAUNCH("batch large-graph launch");
         if (P->side) {
-            const hipError_t e = hipEventRecord(P->join, P->side);
-            if (e != hipSuccess) return fail_hip(e, "recording the large-graph join");
+            hipError_t e = hipEventRecord(P->join, P->side);
+            if (e == hipSuccess && P->side2) e = hipEventRecord(P->join2, P->side2);
+            if (e != hipSuccess) return fail_hip(e, "recording the large-graph joins");
         }
     }
     if (P->nbig + P->nsmall > 0) {
@@ -2374,8 +2420,9 @@ int lexbfs_batch_plan_launch(const lexbfs_batch_plan_t *P, void *stream)
     }
     LX_CHECK_LAUNCH("batch launch");
     if (P->nlarge > 0 && P->side) {
-        const hipError_t e = hipStreamWaitEvent(s, P->join, 0);
-        if (e != hipSuccess) return fail_hip(e, "joining the large-graph stream");
+        hipError_t e = hipStreamWaitEvent(s, P->join, 0);
+        if (e == hipSuccess && P->side2) e = hipStreamWaitEvent(s, P->join2, 0);
+        if (e != hipSuccess) return fail_hip(e, "joining the large-graph streams");
     }
     return LEXBFS_OK;
 }

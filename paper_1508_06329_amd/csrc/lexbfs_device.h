@@ -751,33 +751,31 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         }
 
         // Phase A: count the neighbours of every hit class; record the parent.
-        // A team of several waves runs it before the selection, whose
-        // barrier then also separates it from phase B. One wavefront needs
-        // no barrier (its LDS operations complete in order), so it selects
-        // the next pivot first and issues that row's load before phase A:
-        // the load then overlaps both phases.
-        uint32_t C0 = 0;  // class of my first neighbour, reused in phase B
-        auto phase_a = [&]() {
-            if (kGroup) {
-                for (uint64_t m = nb; m;) {
-                    const uint32_t C = cls[(int)wbase + ctz64(m)];
-                    const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
-                    tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
-                    m &= ~g;
-                }
-            } else {
-                for (uint64_t m = nb; m; m &= m - 1) {
-                    const int y = (int)wbase + ctz64(m);
-                    const uint32_t C = cls[y];
-                    if (m == nb) C0 = C;
-                    if (kPeo) fp.par[y] = (uint16_t)x;
-                    else parent[y] = (int32_t)x;
-                    tab.inc(C);
-                }
+        uint32_t C0 = 0;     // class of my first neighbour, reused in phase B
+        uint64_t sing = 0;   // my neighbours alone in their class (kGroup)
+        if (kGroup) {
+            // A class of one position cannot split: its neighbour stays put
+            // and the class tables are not touched (no round trip to L2).
+            // The class-start bitmap does not change during phase A.
+            for (uint64_t m = nb; m;) {
+                const uint32_t C = cls[(int)wbase + ctz64(m)];
+                const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
+                const uint32_t nx = C + 1u;
+                if (nx >= (uint32_t)U || ((starts[nx >> 6] >> (nx & 63)) & 1ull)) sing |= g;
+                else tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
+                m &= ~g;
             }
-        };
-        if (NW > 1) phase_a();
-        if (i + 1 == n) break;  // (the last pivot has no unnumbered neighbour)
+        } else {
+            for (uint64_t m = nb; m; m &= m - 1) {
+                const int y = (int)wbase + ctz64(m);
+                const uint32_t C = cls[y];
+                if (m == nb) C0 = C;
+                if (kPeo) fp.par[y] = (uint16_t)x;
+                else parent[y] = (int32_t)x;
+                tab.inc(C);
+            }
+        }
+        if (i + 1 == n) break;
 
         // Next pivot (see the header comment). The candidate class is the top
         // class, or -- when x emptied it -- the class directly below, i.e.
@@ -835,16 +833,13 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         xcls = adj ? (uint32_t)U - c_adj : cand;
         // The next pivot's row first: the latency that bounds the step.
         const uint64_t rwn = rowbase[(int64_t)xn * W];  // past the last vertex: masked by um
-        // The next pivot's parent: x when it is one of x's neighbours (its
-        // parent entry may not be written yet), else unchanged by this step.
-        const uint32_t pn = kPeo ? (adj ? x : (uint32_t)fp.par[xn]) : kNoParent;
+        const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
         const uint64_t rpn = kPeo ? rowbase[(int64_t)(pn != kNoParent ? pn : xn) * W] : 0ull;  // used if p exists
-        if (NW == 1) phase_a();
 
         // Phase B: move the neighbours to the upper part of their class; the
         // last neighbour of a class to leave closes it.
         if (kGroup) {
-            for (uint64_t m = nb; m;) {
+            for (uint64_t m = nb & ~sing; m;) {
                 const uint32_t C = cls[(int)wbase + ctz64(m)];
                 const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);
                 const uint32_t cg = (uint32_t)__popcll(g);
