@@ -753,11 +753,40 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         // Phase A: count the neighbours of every hit class; record the parent.
         uint32_t C0 = 0;     // class of my first neighbour, reused in phase B
         uint64_t sing = 0;   // my neighbours alone in their class (kGroup)
+        // kGroup: my neighbours in their first class, whether that class
+        // needs the tables, and the wave's shared handling of it (below).
+        uint64_t gf = 0ull, act = 0ull;
+        bool lf = false, agg = false;
+        uint32_t cw = 0u, wtot = 0u;
         if (kGroup) {
             // A class of one position cannot split: its neighbour stays put
             // and the class tables are not touched (no round trip to L2).
             // The class-start bitmap does not change during phase A.
-            for (uint64_t m = nb; m;) {
+            // Each lane's first class is handled by its wave at once: when
+            // the lanes whose first class needs the tables all have the same
+            // one (a pivot adjacent to a run of ids, as in a clique), a
+            // single atomic adds the wave's count, instead of one per lane on
+            // one address -- those serialise in L2 and hold up the memory
+            // path of the CU for every wave.
+            uint32_t Cf = 0u;
+            if (nb) {
+                Cf = cls[(int)wbase + ctz64(nb)];
+                gf = chunk_match(cls, nb, Cf, vbase, sh, K);
+                const uint32_t nx = Cf + 1u;
+                if (nx >= (uint32_t)U || ((starts[nx >> 6] >> (nx & 63)) & 1ull)) sing |= gf;
+                else lf = true;
+            }
+            act = __ballot(lf);
+            cw = act ? (uint32_t)__shfl((int)Cf, ctz64(act), kWave) : 0u;
+            agg = act != 0ull && __ballot(lf && Cf == cw) == act;
+            const uint32_t cf = lf ? (uint32_t)__popcll(gf) : 0u;
+            if (agg) {
+                wtot = wave_sum_dpp(cf);
+                if ((uint32_t)(t & 63) == (uint32_t)ctz64(act)) tab.add(cw, wtot);
+            } else if (lf) {
+                tab.add(Cf, cf);
+            }
+            for (uint64_t m = nb & ~gf; m;) {
                 const uint32_t C = cls[(int)wbase + ctz64(m)];
                 const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
                 const uint32_t nx = C + 1u;
@@ -839,7 +868,26 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
         // Phase B: move the neighbours to the upper part of their class; the
         // last neighbour of a class to leave closes it.
         if (kGroup) {
-            for (uint64_t m = nb & ~sing; m;) {
+            if (agg) {  // the wave's shared first class (phase A)
+                const uint32_t C = cw;
+                const uint32_t c = tab.word(C) & 0xFFFFu;
+                const uint32_t last = tab.last(C);
+                const bool split = c < last - C + 1;
+                const uint32_t nw = last + 1 - c;
+                if (split && lf)
+                    for (uint64_t q = gf; q; q &= q - 1) cls[(int)wbase + ctz64(q)] = (uint16_t)nw;
+                if ((uint32_t)(t & 63) == (uint32_t)ctz64(act)) {
+                    if (split) tab.set_last(nw, last);
+                    if ((tab.moved_by(C, wtot) >> 16) + wtot == c) {  // the last group out closes C
+                        tab.clear(C);
+                        if (split) {
+                            tab.set_last(C, nw - 1);
+                            atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
+                        }
+                    }
+                }
+            }
+            for (uint64_t m = nb & ~sing & (agg ? ~gf : ~0ull); m;) {
                 const uint32_t C = cls[(int)wbase + ctz64(m)];
                 const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);
                 const uint32_t cg = (uint32_t)__popcll(g);
