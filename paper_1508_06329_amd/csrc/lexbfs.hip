@@ -567,12 +567,12 @@ template <class Team, bool kMcs, bool kIlv = false>
 __device__ void batch_graph(const Team &tm, const GDesc &g, void *region, uint32_t flags)
 {
     if (kMcs) {
-        mcs_team<Team, true>(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent,
-                             carve_mcs(region, g.n, Team::kSize, true, g.failkey));
+        mcs_team<Team, true, 2>(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent,
+                                carve_mcs(region, g.n, Team::kSize, true, g.failkey));
     } else {
         BatchLayout B = carve_batch(region, g.n, Team::kSize, g.failkey);
-        lexbfs_team<Team, LdsTables, true, kIlv>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent,
-                                                  B.L.starts, B.L.cls, B.L.tab, B.L.red, B.fp);
+        lexbfs_team<Team, LdsTables, true, kIlv, 16, 2>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank, g.parent,
+                                                         B.L.starts, B.L.cls, B.L.tab, B.L.red, B.fp);
     }
     tm.sync_mem();  // order, rank, parent and the failing rank visible to the team
     if (!(flags & kFlagOrderOnly)) finish_graph(tm, g, flags, carve_finish(region, g.wn, Team::kWaves));

@@ -523,32 +523,77 @@ __device__ __forceinline__ LdsLayoutG carve_lds_g(void *base, int n, int team)
     return L;
 }
 
-// Which of 8 consecutive 16-bit class ids (one 16-byte LDS read) equal c:
-// bit j for entry j.
+// Class-id matching on packed 16-bit halves: after xor with the pattern,
+// one v_pk_min_u16 against (1, 1) leaves 0 in a half that matched and 1 in
+// one that did not, two ids per instruction.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// (1, 1) in a register whose value the compiler does not see: with the
+// constant in view it turns min(x, 1) back into a compare and a select per
+// half.
+__device__ __forceinline__ uint32_t pk_ones()
+{
+    uint32_t r;
+    __asm__("s_mov_b32 %0, 0x10001" : "=s"(r));
+    return r;
+}
+
+// 8 class ids (one 16-byte LDS read) against pat = c | c << 16: bit 2k is
+// set iff the low id of word k differs from c, bit 16 + 2k iff its high id
+// does.
+__device__ __forceinline__ uint32_t diff8(uint4 q, uint32_t pat, uint32_t ones)
+{
+    auto nz = [ones](uint32_t x) {
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, x),
+                                                                      __builtin_bit_cast(u16x2, ones)));
+    };
+    return nz(q.x ^ pat) | nz(q.y ^ pat) << 2 | nz(q.z ^ pat) << 4 | nz(q.w ^ pat) << 6;
+}
+
+// Which of 8 consecutive 16-bit class ids equal c: bit j for entry j.
 __device__ __forceinline__ uint32_t match8(uint4 q, uint32_t c)
 {
-    const uint32_t pat = c | (c << 16);
-    const uint32_t x0 = q.x ^ pat, x1 = q.y ^ pat, x2 = q.z ^ pat, x3 = q.w ^ pat;
-    return ((x0 & 0xFFFFu) == 0) | ((x0 >> 16) == 0) << 1 | ((x1 & 0xFFFFu) == 0) << 2 | ((x1 >> 16) == 0) << 3 |
-           ((x2 & 0xFFFFu) == 0) << 4 | ((x2 >> 16) == 0) << 5 | ((x3 & 0xFFFFu) == 0) << 6 | ((x3 >> 16) == 0) << 7;
+    const uint32_t w = diff8(q, c | (c << 16), pk_ones());
+    return ~(w | (w >> 15)) & 0xFFu;  // high-id flags 16 + 2k move to 2k + 1
+}
+
+// The same for 16 consecutive ids in two groups: bit j for entry j.
+__device__ __forceinline__ uint32_t match16(uint4 a, uint4 b, uint32_t c)
+{
+    const uint32_t pat = c | (c << 16), ones = pk_ones();
+    const uint32_t w = diff8(a, pat, ones) | diff8(b, pat, ones) << 8;
+    return ~(w | (w >> 15)) & 0xFFFFu;
 }
 
 // Bits of my unnumbered vertices `um` (word positions) whose class is c.
+// The needed 16-byte groups of ids are requested kG at a time, each batch
+// before any of it is used: one LDS round trip per kG groups, not one per
+// group. kG is the most a team's chunks need (chunks of up to 8 kG ids take
+// one round trip; larger ones stay correct) and bounds the registers held.
+template <int kG = 8>
 __device__ __forceinline__ uint64_t chunk_match(const uint16_t *cls, uint64_t um, uint32_t c, int vbase, int sh, int K)
 {
     if (!um) return 0;
     uint64_t res = 0;
     if (K >= 8) {
-        const uint32_t pat = c | (c << 16);
         const uint4 *p = (const uint4 *)(cls + vbase);
-        for (int j = 0; j < K; j += 8) {
-            if (!((um >> (sh + j)) & 0xFFull)) continue;
-            const uint4 q = p[j >> 3];
-            const uint32_t x0 = q.x ^ pat, x1 = q.y ^ pat, x2 = q.z ^ pat, x3 = q.w ^ pat;
-            const uint32_t m8 = ((x0 & 0xFFFFu) == 0) | ((x0 >> 16) == 0) << 1 | ((x1 & 0xFFFFu) == 0) << 2 |
-                                ((x1 >> 16) == 0) << 3 | ((x2 & 0xFFFFu) == 0) << 4 | ((x2 >> 16) == 0) << 5 |
-                                ((x3 & 0xFFFFu) == 0) << 6 | ((x3 >> 16) == 0) << 7;
-            res |= (uint64_t)m8 << (sh + j);
+        const uint32_t nc = ~(c | (c << 16));  // matches no id
+        for (int j0 = 0; j0 < K; j0 += 8 * kG) {
+            uint4 q[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                const int b = j0 + 8 * j;
+                q[j] = make_uint4(nc, nc, nc, nc);
+                if (b < K && ((um >> (sh + b)) & 0xFFull)) q[j] = p[b >> 3];
+            }
+#pragma unroll
+            for (int j = 0; j < kG; j += 2) {
+                const int b = j0 + 8 * j;
+                if (b >= K) break;
+                // A second group past K holds no matches (filled above).
+                const uint32_t m = j + 1 < kG ? match16(q[j], q[j + 1 < kG ? j + 1 : j], c) : match8(q[j], c);
+                res |= (uint64_t)m << (sh + b);
+            }
         }
         return res & um;
     }
@@ -626,8 +671,11 @@ __device__ __forceinline__ uint32_t pick_key_ilv(uint64_t top, uint64_t nb, int 
 // kIlv: ties go to the smallest interleaved rank (ilv_rank) instead of the
 // smallest id. kPre: the largest K whose class ids the gone case loads
 // early (8, 16 or 32; wider K matches from LDS), a register budget.
-template <class Team, class Tabs, bool kPeo = false, bool kIlv = false, int kPre = 16>
-__device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
+// kMatchG: 16-byte groups of class ids a chunk match requests per LDS round
+// trip (8 covers K = 64 at once; batch teams, K <= 16, use 2), also a
+// register budget.
+template <class Team, class Tabs, bool kPeo = false, bool kIlv = false, int kPre = 16, int kMatchG = 8>
+__device__ __forceinline__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, const int32_t *row_ptr_,
                             int32_t *order_, int32_t *rank_, int32_t *parent_, uint64_t *starts, uint16_t *cls,
                             const Tabs &tab, uint32_t *red, const FusedPeo &fp = FusedPeo{})
 {
@@ -768,13 +816,19 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             // single atomic adds the wave's count, instead of one per lane on
             // one address -- those serialise in L2 and hold up the memory
             // path of the CU for every wave.
+            // A one-position class holds only the neighbour that named it,
+            // so its members need no match over the chunk.
             uint32_t Cf = 0u;
             if (nb) {
                 Cf = cls[(int)wbase + ctz64(nb)];
-                gf = chunk_match(cls, nb, Cf, vbase, sh, K);
                 const uint32_t nx = Cf + 1u;
-                if (nx >= (uint32_t)U || ((starts[nx >> 6] >> (nx & 63)) & 1ull)) sing |= gf;
-                else lf = true;
+                if (nx >= (uint32_t)U || ((starts[nx >> 6] >> (nx & 63)) & 1ull)) {
+                    gf = nb & (0ull - nb);
+                    sing |= gf;
+                } else {
+                    gf = chunk_match<kMatchG>(cls, nb, Cf, vbase, sh, K);
+                    lf = true;
+                }
             }
             act = __ballot(lf);
             cw = act ? (uint32_t)__shfl((int)Cf, ctz64(act), kWave) : 0u;
@@ -788,10 +842,14 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             }
             for (uint64_t m = nb & ~gf; m;) {
                 const uint32_t C = cls[(int)wbase + ctz64(m)];
-                const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);  // my neighbours in C
                 const uint32_t nx = C + 1u;
-                if (nx >= (uint32_t)U || ((starts[nx >> 6] >> (nx & 63)) & 1ull)) sing |= g;
-                else tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
+                uint64_t g = m & (0ull - m);
+                if (nx >= (uint32_t)U || ((starts[nx >> 6] >> (nx & 63)) & 1ull)) {
+                    sing |= g;
+                } else {
+                    g = chunk_match<kMatchG>(cls, m, C, vbase, sh, K);  // my neighbours in C
+                    tab.add(C, (uint32_t)__popcll(g));  // parents: derive_parents after the order
+                }
                 m &= ~g;
             }
         } else {
@@ -834,11 +892,13 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             if (K >= 8 && K <= kPre) {
                 uint64_t mm = 0ull;
 #pragma unroll
-                for (int q = 0; q < kQ; ++q)
-                    if (8 * q < K) mm |= (uint64_t)match8(cc[q], cand) << (8 * q);
+                for (int q = 0; q < kQ; q += 2)  // ids past the chunk: masked by um
+                    if (8 * q < K)
+                        mm |= (uint64_t)(q + 1 < kQ ? match16(cc[q], cc[q + 1 < kQ ? q + 1 : q], cand)
+                                                    : match8(cc[q], cand)) << (8 * q);
                 top = (mm << sh) & um;
             } else {
-                top = chunk_match(cls, um, cand, vbase, sh, K);
+                top = chunk_match<kMatchG>(cls, um, cand, vbase, sh, K);
             }
         }
         // One reduction: the selection key (max) and two 16-bit sums packed
@@ -889,7 +949,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
             }
             for (uint64_t m = nb & ~sing & (agg ? ~gf : ~0ull); m;) {
                 const uint32_t C = cls[(int)wbase + ctz64(m)];
-                const uint64_t g = chunk_match(cls, m, C, vbase, sh, K);
+                const uint64_t g = chunk_match<kMatchG>(cls, m, C, vbase, sh, K);
                 const uint32_t cg = (uint32_t)__popcll(g);
                 const uint32_t c = tab.word(C) & 0xFFFFu;
                 const uint32_t last = tab.last(C);
@@ -977,7 +1037,7 @@ __device__ void lexbfs_team(const Team &tm, int n, const uint64_t *bits_, int64_
                 const uint32_t C = ((uint32_t)w << 6) | (uint32_t)b;
                 const uint64_t above = b == 63 ? 0ull : sw & (~0ull << (b + 1));
                 const uint32_t Ec = above ? (((uint32_t)w << 6) | (uint32_t)ctz64(above)) : E;
-                const uint64_t mine = chunk_match(cls, um, C, vbase, sh, K);
+                const uint64_t mine = chunk_match<kMatchG>(cls, um, C, vbase, sh, K);
                 const uint32_t cnt_l = (uint32_t)__popcll(mine);
                 uint32_t r = i0 + (U0 - Ec) + tm.exclusive_scan(cnt_l, red + par * 2 * NW);
                 for (uint64_t q = mine; q; q &= q - 1) {
@@ -1092,7 +1152,7 @@ __device__ __forceinline__ uint32_t prev_start(const uint64_t *starts, const uin
 }
 
 template <class Team>
-__device__ void lexbfs_team_compact(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_,
+__device__ __forceinline__ void lexbfs_team_compact(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_,
                                     int32_t *rank_, int32_t *parent_, const CompactLayout &L)
 {
     LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
@@ -1380,13 +1440,15 @@ __device__ __forceinline__ uint32_t mcs_lane_best(const uint16_t *cnt, uint64_t 
     return best;
 }
 
+template <int kG>
 __device__ __forceinline__ uint64_t mcs_lane_match(const uint16_t *cnt, uint64_t um, uint32_t c, int vbase, int sh, int K)
 {
-    return chunk_match(cnt, um, c, vbase, sh, K);
+    return chunk_match<kG>(cnt, um, c, vbase, sh, K);
 }
 
-template <class Team, bool kPeo = false>
-__device__ void mcs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_, int32_t *rank_,
+// kMatchG: 16-byte groups of a chunk matched per LDS round trip (chunk_match).
+template <class Team, bool kPeo = false, int kMatchG = 8>
+__device__ __forceinline__ void mcs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W, int32_t *order_, int32_t *rank_,
                          int32_t *parent_, const McsLayout &L)
 {
     LX_GLOBAL const uint64_t *__restrict__ bits = as_global(bits_);
@@ -1473,7 +1535,7 @@ __device__ void mcs_team(const Team &tm, int n, const uint64_t *bits_, int64_t W
             k = tm.max_all(mcs_lane_best(cnt, um, vbase, sh, K), red + par * 2 * NW);
             par ^= 1;
             cmax = (k >> 16) - 1u;
-            top = mcs_lane_match(cnt, um, cmax, vbase, sh, K);
+            top = mcs_lane_match<kMatchG>(cnt, um, cmax, vbase, sh, K);
         }
         const uint32_t xn = 0xFFFFu - (k & 0xFFFFu);
         const uint32_t pn = kPeo ? (uint32_t)fp.par[xn] : kNoParent;
