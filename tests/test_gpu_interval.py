@@ -92,8 +92,10 @@ def test_full_size():
 
 
 def test_compact_layout_sizes():
-    """n = 20,000-32,768: the compact LDS form of the LexBFS kernel (class
-    ends from the class-start bitmap) in every sweep."""
+    """n = 25,000 and 32,768: the compact LDS form of the LexBFS kernel (class
+    ends from the class-start bitmap) in every sweep. n = 20,000 on 512 lanes
+    is the largest LDS-table case (162,640 bytes of LDS, 64 vertices per
+    lane) for the LexBFS+ sweep."""
     check_interval(gg.intervals(25000, 10, 31), tag="N=25000 unit")
     check_interval(gg.intervals(32768, 10, 32, unit=False), tag="N=32768 mixed")
     g = gg.gnp(20000, 0.0005, 33)
