@@ -47,6 +47,16 @@ def _on_stream(stream: Optional[torch.cuda.Stream], *tensors: Optional[torch.Ten
             t.record_stream(stream)
 
 
+def _zeros_on(shape, device, stream: Optional[torch.cuda.Stream]) -> torch.Tensor:
+    """A zero-filled int32 device tensor whose fill runs on `stream` (the
+    current stream if None): ahead of the kernels later queued there, which
+    a fill on another stream would not be."""
+    if stream is None:
+        return torch.zeros(shape, dtype=torch.int32, device=device)
+    with torch.cuda.stream(stream):
+        return torch.zeros(shape, dtype=torch.int32, device=device)
+
+
 def _wait(stream: Optional[torch.cuda.Stream]) -> None:
     (stream if stream is not None else torch.cuda.current_stream()).synchronize()
 
@@ -69,6 +79,30 @@ class DeviceGraph:
             ci = torch.zeros(1, dtype=torch.int32, device=device)[:0]
         bits = torch.from_numpy(g.bits.view("int64")).to(device)
         return cls(g.n, g.W, rp, ci, bits)
+
+    @classmethod
+    def from_host_csr(cls, g, device="cuda", stream=None) -> "DeviceGraph":
+        """From a host CSR only (an object with n, row_ptr and col_idx numpy
+        arrays): the CSR is staged in pinned host memory and copied
+        asynchronously on `stream` (the current stream if None), then the
+        bitset is built on the device there (lexbfs_build_bitset). Only the
+        CSR crosses PCIe, and the call returns without waiting; work queued
+        on the same stream afterwards sees the finished graph."""
+        import numpy as np
+
+        dev = torch.device(device)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        n = int(g.n)
+        nnz = int(g.row_ptr[n]) if n > 0 else 0
+        rp_h = torch.from_numpy(np.ascontiguousarray(g.row_ptr[: n + 1], dtype=np.int32)).pin_memory()
+        ci_h = torch.from_numpy(np.ascontiguousarray(g.col_idx[:nnz], dtype=np.int32)).pin_memory()
+        with torch.cuda.stream(s):
+            rp = torch.empty(rp_h.numel(), dtype=torch.int32, device=dev)
+            ci = torch.empty(nnz, dtype=torch.int32, device=dev)
+            rp.copy_(rp_h, non_blocking=True)
+            if nnz:
+                ci.copy_(ci_h, non_blocking=True)
+        return cls.from_csr(n, rp, ci, stream=s)
 
     @classmethod
     def from_csr(cls, n: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, words_per_row: Optional[int] = None,
@@ -304,7 +338,7 @@ def chordal_test(g: DeviceGraph, flags: int = 0, stream=None, outputs: bool = Tr
     lib = _lib.load()
     n = g.n
     dev = g.device
-    res = torch.zeros(8, dtype=torch.int32, device=dev)
+    res = _zeros_on(8, dev, stream)
     outs = lexbfs_outputs_t()
     tens = {}
     if outputs:
@@ -376,7 +410,7 @@ def chordal_test_batch(graphs: Sequence[DeviceGraph], flags: int = 0, stream=Non
             for k, v in t.items():
                 setattr(outs_arr[i], k, v.data_ptr())
     if res is None:
-        res = torch.zeros((count, 8), dtype=torch.int32, device=dev)
+        res = _zeros_on((count, 8), dev, stream)
     need = int(lib.lexbfs_batch_workspace_bytes(arr, count))
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)

@@ -261,7 +261,7 @@ class SerialExecutor(GpuExecutor):
         super().__init__(device, streams={"all": 1}, outputs=outputs)
 
     def start(self, reqs: Sequence[Request], cls: str = "all"):
-        from . import _lib, lexbfs_outputs_t
+        from . import _lib, _zeros_on, lexbfs_outputs_t
 
         torch = self.torch
         s = self.streams["all"][0]
@@ -269,7 +269,7 @@ class SerialExecutor(GpuExecutor):
         s.wait_event(up)
         handle = {"stream": s, "reqs": reqs, "dgs": dgs, "plan": None, "singles": []}
         for i, g in enumerate(dgs):
-            res = torch.zeros(8, dtype=torch.int32, device=self.dev)
+            res = _zeros_on(8, self.dev, s)  # the fill runs on s, ahead of the test
             outs = lexbfs_outputs_t()
             tens = {}
             if self.outputs:

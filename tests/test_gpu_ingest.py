@@ -60,3 +60,22 @@ def test_whole_path_from_device_csr():
         ref = oracle.chordal_test(g)
         assert np.array_equal(r.order.cpu().numpy(), ref.order)
         assert r.chordal == ref.chordal and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()
+
+
+def test_whole_path_from_host_csr_on_a_side_stream():
+    """Pinned staging and asynchronous CSR copies on a side stream, the
+    bitset built there, and the test queued behind it on the same stream:
+    bit-exact bitsets and the oracle's results, for graphs with and without
+    edges."""
+    side = torch.cuda.Stream()
+    graphs = [gg.plant(gg.subtree(5000, 1200, 10, 11), 6, 11), gg.gnp(3000, 0.003, 12), gg.from_edges(70, [])]
+    for g in graphs:
+        print(f"[ingest] host CSR {g.name} n={g.n}", flush=True)
+        dg = lx.DeviceGraph.from_host_csr(g, DEV, stream=side)
+        r = lx.chordal_test(dg, stream=side)  # sync=True: waits on the side stream
+        side.synchronize()
+        bits = dg.bits.cpu().numpy().view(np.uint64)[: g.n * dg.W].reshape(g.n, dg.W)
+        assert np.array_equal(bits, oracle.bitset_from_csr(g.n, g.row_ptr, g.col_idx, dg.W)), g.name
+        ref = oracle.chordal_test(g)
+        assert np.array_equal(r.order.cpu().numpy(), ref.order), g.name
+        assert r.chordal == ref.chordal and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()
