@@ -390,6 +390,7 @@ template <int T, int kMode, bool kIlv = false>
 __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
 {
     extern __shared__ uint64_t lds[];
+    vgpr_headroom<T>();
     if (threadIdx.x == 0 && g.failkey) *g.failkey = kNoFail;
     if (kMode == kModeCompact) {
         BlockTeam<T, false> tm{(int)threadIdx.x};
@@ -423,6 +424,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_mcs_single(GDesc g)
 {
     extern __shared__ uint64_t lds[];
+    vgpr_headroom<T>();
     if (threadIdx.x == 0 && g.failkey) *g.failkey = kNoFail;
     BlockTeam<T, false> tm{(int)threadIdx.x};
     mcs_team(tm, g.n, g.bits, g.W, g.order, g.rank, g.parent, carve_mcs(lds, g.n, T, false, nullptr));
@@ -780,6 +782,7 @@ __global__ __launch_bounds__(T) void k_batch_large(const GDesc *__restrict__ gds
                                                    uint32_t flags, int lds_limit)
 {
     extern __shared__ uint64_t lds[];
+    vgpr_headroom<T>();
     const GDesc g = gds[which[blockIdx.x]];
     if (kMcs) {
         BlockTeam<T, false> tm{(int)threadIdx.x};

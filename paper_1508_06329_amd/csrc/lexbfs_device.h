@@ -169,6 +169,20 @@ __device__ __forceinline__ void g_store_i(int32_t *p, int32_t v)
 // ---------------------------------------------------------------------------
 // Teams
 // ---------------------------------------------------------------------------
+// Register headroom of the kernels that run one 512- or 1,024-lane team per
+// workgroup: an empty asm that clobbers v95 at entry raises the kernel's VGPR
+// allocation to at least 96 and emits no instruction. A build of the
+// 1,024-lane LexBFS kernel with an allocation of exactly 88 VGPRs and live
+// values in v84-v87 returned wrong orders on gfx950, on graphs whose pivots
+// have thousands of neighbours; the identical machine code with a 96-register
+// allocation returned the right ones, as do the builds below 84 registers.
+// At 4 (or 2) waves per SIMD the larger allocation costs no occupancy.
+template <int T>
+__device__ __forceinline__ void vgpr_headroom()
+{
+    if constexpr (T >= 512) __asm__ volatile("" ::: "v95");
+}
+
 // Max of a 32-bit value over the 64 lanes with DPP (all lanes active); the
 // result is uniform.
 template <int CTRL, int ROW_MASK>

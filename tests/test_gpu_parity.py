@@ -124,6 +124,34 @@ def test_workload_split_65536_full():
     assert not ref.chordal and len(ref.cycle) == 4
 
 
+# Split graphs at n = 65,536 (1,024-lane team, class tables in L2) whose
+# pivots have thousands of neighbours spread over every lane from the first
+# step on: the clique's vertices hold the next pivot at every clique step,
+# so a lost or wrong contribution of their lane to a selection shows at once.
+def heavy_split(K):
+    return gg.split(K, 65536 - K, min(64, max(1, K // 2)), 1000 + K)
+
+
+def moved_clique(base):
+    """The 32-clique split graph with ids [0, 64) and [base, base + 64)
+    swapped: the clique sits on another lane and wave."""
+    g = heavy_split(32)
+    perm = np.arange(g.n, dtype=np.int64)
+    perm[0:64] = np.arange(base, base + 64)
+    perm[base:base + 64] = np.arange(64)
+    return gg.relabel(g, perm)
+
+
+@pytest.mark.parametrize("K", [16, 32, 128, 512, 2048])
+def test_split_heavy_steps_65536(K):
+    check_single(heavy_split(K), tag=f"heavy split, clique of {K}")
+
+
+@pytest.mark.parametrize("base", [64, 20480, 21568])
+def test_split_heavy_steps_clique_on_other_lanes(base):
+    check_single(moved_clique(base), tag=f"heavy split, clique at {base}")
+
+
 # ---------------------------------------------------------------------------
 # lexbfs_order entry point, determinism
 # ---------------------------------------------------------------------------
@@ -333,6 +361,14 @@ def test_batch_size_limit():
     # one above: the 1024-lane tier takes it
     big = gg.from_edges(lim + 1, [(i, i + 1) for i in range(lim)] + [(0, lim)], "C_lim+1")
     check_batch([big, gg.gnp(200, 0.05, 34)], tag="one above the 256-lane tier")
+
+
+def test_batch_large_tier_heavy_steps():
+    """The 1,024-lane batch tier on n = 65,536 split graphs with heavy steps
+    (class tables in L2), beside small graphs."""
+    graphs = [heavy_split(32), moved_clique(21568), heavy_split(512), gg.gnp(700, 8 / 699, 31),
+              gg.subtree(3000, 750, 8, 32)]
+    check_batch(graphs, tag="1024-lane tier, heavy split graphs")
 
 
 def test_batch_large_tier_with_plan_and_one_shot():
