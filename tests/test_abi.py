@@ -218,3 +218,52 @@ def test_validate_argument_errors(lib):
     g = fake_graph(0, nnz=0)
     assert lib.lexbfs_validate(ctypes.byref(g), None, 0, None) == _lib.LEXBFS_OK
     assert lib.lexbfs_strerror(_lib.LEXBFS_EGRAPH) == b"graph violates the input contract"
+
+
+def _device_code_object(tmp_path):
+    """The gfx950 code object inside the built library (its offload bundle)."""
+    llvm = "/opt/rocm/llvm/bin"
+    bundler = os.path.join(llvm, "clang-offload-bundler")
+    if not os.path.exists(bundler):
+        pytest.skip("ROCm offload bundler not available")
+    fatbin = tmp_path / "lib.hipfb"
+    co = tmp_path / "lib.co"
+    subprocess.run(["objcopy", f"--dump-section=.hip_fatbin={fatbin}", _lib.LIB_PATH], check=True)
+    subprocess.run([bundler, "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--input={fatbin}",
+                    f"--output={co}", "--unbundle"], check=True)
+    return llvm, co
+
+
+def test_large_team_kernels_reserve_register_headroom(lib, tmp_path):
+    """Kernels that run one 512- or 1,024-lane team per workgroup allocate at
+    least 96 VGPRs (the v95 clobber at their entry): the 1,024-lane LexBFS
+    kernel gave wrong orders when its allocation was exactly 88 registers with
+    v84-v87 in use, and right ones with the same code at 96. The allocation
+    is read from each kernel descriptor (COMPUTE_PGM_RSRC1, VGPR granules of 8)."""
+    import struct
+
+    llvm, co = _device_code_object(tmp_path)
+    syms = subprocess.run([os.path.join(llvm, "llvm-readelf"), "-sW", str(co)], capture_output=True, text=True,
+                          check=True).stdout
+    secs = subprocess.run([os.path.join(llvm, "llvm-readelf"), "-SW", str(co)], capture_output=True, text=True,
+                          check=True).stdout
+    sections = []
+    for line in secs.splitlines():
+        m = re.match(r"\s*\[\s*\d+\]\s+(\S+)\s+\S+\s+([0-9a-f]+)\s+([0-9a-f]+)\s+([0-9a-f]+)", line)
+        if m:
+            sections.append((int(m.group(2), 16), int(m.group(3), 16), int(m.group(4), 16)))
+    data = co.read_bytes()
+    large = re.compile(r"(k_lexbfs_single|k_mcs_single|k_batch_large)ILi(512|1024)E")
+    checked = 0
+    for line in syms.splitlines():
+        f = line.split()
+        if len(f) < 8 or not f[7].endswith(".kd") or not large.search(f[7]):
+            continue
+        addr = int(f[1], 16)
+        sec = next(s for s in sections if s[0] <= addr < s[0] + s[2])
+        kd = data[sec[1] + addr - sec[0]: sec[1] + addr - sec[0] + 64]
+        rsrc1 = struct.unpack_from("<I", kd, 48)[0]
+        vgprs = ((rsrc1 & 0x3F) + 1) * 8
+        assert vgprs >= 96, (f[7], vgprs)
+        checked += 1
+    assert checked >= 14, checked  # every instantiation of the three kernels at 512 and 1,024 lanes
