@@ -228,7 +228,9 @@ def _device_code_object(tmp_path):
         pytest.skip("ROCm offload bundler not available")
     fatbin = tmp_path / "lib.hipfb"
     co = tmp_path / "lib.co"
-    subprocess.run(["objcopy", f"--dump-section=.hip_fatbin={fatbin}", _lib.LIB_PATH], check=True)
+    # Section contents into a file of their own: the library itself (loaded
+    # in this process) is only read.
+    subprocess.run(["objcopy", "-O", "binary", "--only-section=.hip_fatbin", _lib.LIB_PATH, str(fatbin)], check=True)
     subprocess.run([bundler, "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--input={fatbin}",
                     f"--output={co}", "--unbundle"], check=True)
     return llvm, co
