@@ -152,6 +152,25 @@ def test_split_heavy_steps_clique_on_other_lanes(base):
     check_single(moved_clique(base), tag=f"heavy split, clique at {base}")
 
 
+HEAVY_SMALLER = [(1024, 16), (1024, 64), (4096, 16), (4096, 256), (16384, 64), (16384, 256), (32768, 16),
+                 (32768, 256)]
+
+
+def heavy_split_n(n, K):
+    return gg.split(K, n - K, min(64, max(1, K // 2)), 7000 + K + n)
+
+
+@pytest.mark.parametrize("n,K", HEAVY_SMALLER)
+def test_split_heavy_steps_smaller_teams(n, K):
+    """The same heavy steps on the 128-, 256- and 512-lane teams (LDS class
+    tables, compact layout at n = 32,768)."""
+    check_single(heavy_split_n(n, K), tag=f"heavy split n={n}, clique of {K}")
+
+
+def test_batch_heavy_steps_every_tier():
+    check_batch([heavy_split_n(n, K) for n, K in HEAVY_SMALLER], tag="heavy split graphs, n = 1,024 .. 32,768")
+
+
 # ---------------------------------------------------------------------------
 # lexbfs_order entry point, determinism
 # ---------------------------------------------------------------------------
