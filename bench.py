@@ -143,17 +143,18 @@ def kernel_source_sha():
 
 
 def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+    """HBM bytes per launch of `kernel` (lexbfs, sweep) on `workload` from the
+    workload's committed counter summary, profiles/lexbfs_<workload>_pmc.txt
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"lexbfs_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
     want = kernel_source_sha()
     for line in open(path):
         if line.startswith("traffic:"):
             kv = dict(t.split("=", 1) for t in line.split()[1:])
-            if kv.get("source_sha256") == want:
+            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha256") == want:
                 return float(kv["bytes_per_launch"])
     return None
 
