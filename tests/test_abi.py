@@ -269,3 +269,22 @@ def test_large_team_kernels_reserve_register_headroom(lib, tmp_path):
         assert vgprs >= 96, (f[7], vgprs)
         checked += 1
     assert checked >= 14, checked  # every instantiation of the three kernels at 512 and 1,024 lanes
+
+
+def test_no_kernel_uses_the_top_of_an_88_register_allocation(lib, tmp_path):
+    """No kernel of the library is built with 85-88 VGPRs (an allocation of
+    88 with v84-v87 in use): the configuration that gave wrong LexBFS orders
+    with otherwise correct machine code. Counts from the code object's
+    kernel metadata."""
+    llvm, co = _device_code_object(tmp_path)
+    notes = subprocess.run([os.path.join(llvm, "llvm-readelf"), "--notes", str(co)], capture_output=True, text=True,
+                           check=True).stdout
+    counts = {}
+    for block in re.split(r"\n\s+- \.", notes):
+        name = re.search(r"\.name:\s+(\S+)", block)
+        vgpr = re.search(r"\.vgpr_count:\s+(\d+)", block)
+        if name and vgpr:
+            counts[name.group(1)] = int(vgpr.group(1))
+    assert len(counts) >= 40, len(counts)
+    bad = {k: v for k, v in counts.items() if 85 <= v <= 88}
+    assert not bad, bad
