@@ -444,6 +444,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_finish_single(GDesc g, uint32_t flags)
 {
     extern __shared__ uint64_t lds[];
+    vgpr_headroom<T>();
     BlockTeam<T, false> tm{(int)threadIdx.x};
     finish_graph(tm, g, flags, carve_finish(lds, g.wn, T / kWave));
 }

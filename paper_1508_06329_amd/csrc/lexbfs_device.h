@@ -170,7 +170,7 @@ __device__ __forceinline__ void g_store_i(int32_t *p, int32_t v)
 // Teams
 // ---------------------------------------------------------------------------
 // Register headroom of the kernels that run one 512- or 1,024-lane team per
-// workgroup: an empty asm that clobbers v95 at entry raises the kernel's VGPR
+// workgroup (LexBFS, MCS, the large batch tier, the single-graph finish): an empty asm that clobbers v95 at entry raises the kernel's VGPR
 // allocation to at least 96 and emits no instruction. A build of the
 // 1,024-lane LexBFS kernel with an allocation of exactly 88 VGPRs and live
 // values in v84-v87 returned wrong orders on gfx950, on graphs whose pivots
