@@ -404,8 +404,20 @@ __global__ __launch_bounds__(T) void k_lexbfs_single(GDesc g)
     } else {
         LdsLayout L = carve_lds(lds, g.n, T);
         BlockTeam<T, false> tm{(int)threadIdx.x};
-        lexbfs_team<BlockTeam<T, false>, LdsTables, false, kIlv, 32>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank,
-                                                                     g.parent, L.starts, L.cls, L.tab, L.red);
+        if constexpr (T >= 512) {
+            // Graphs of 4,097 to about 20,000 vertices (positions below 2^15):
+            // the recorded-member form. Smaller teams match 16 ids or fewer
+            // per lane, which costs less than its extra slot read and decode.
+            LdsTablesSole tab;
+            tab.clast = L.tab.clast;
+            tab.cnt = L.tab.cnt;
+            lexbfs_team<BlockTeam<T, false>, LdsTablesSole, false, kIlv, 32>(tm, g.n, g.bits, g.W, g.rp, g.order,
+                                                                             g.rank, g.parent, L.starts, L.cls, tab,
+                                                                             L.red);
+        } else {
+            lexbfs_team<BlockTeam<T, false>, LdsTables, false, kIlv, 32>(tm, g.n, g.bits, g.W, g.rp, g.order, g.rank,
+                                                                         g.parent, L.starts, L.cls, L.tab, L.red);
+        }
     }
 }
 
@@ -1454,7 +1466,7 @@ int single_mode_T(int n, int &mode)
     const size_t lim_g = dynamic_lds_limit(k_lexbfs_single<T, kModeGlobal>);
     if (!lim_l || !lim_c || !lim_g)
         return fail_code(LEXBFS_EHIP, "querying or raising the LexBFS kernel's LDS limit failed");
-    if (lds_bytes_lds_tables(n, T) <= lim_l) mode = kModeLds;
+    if (n < 32768 && lds_bytes_lds_tables(n, T) <= lim_l) mode = kModeLds;  // positions below 2^15
     else if (lds_bytes_compact(n, T) <= lim_c) mode = kModeCompact;
     else if (lds_bytes_global_tables(n, T) <= lim_g) mode = kModeGlobal;
     else return fail_code(LEXBFS_ETOOBIG, "graph state does not fit the workgroup LDS");

@@ -391,6 +391,7 @@ struct LdsTables {
     uint16_t *clast;
     uint32_t *cnt;
     static constexpr bool kInLds = true;
+    static constexpr bool kSole = false;  // see LdsTablesSole
     __device__ __forceinline__ uint32_t last(uint32_t c) const { return clast[c]; }
     __device__ __forceinline__ void set_last(uint32_t c, uint32_t v) const { clast[c] = (uint16_t)v; }
     __device__ __forceinline__ uint32_t word(uint32_t c) const { return cnt[c]; }
@@ -402,6 +403,26 @@ struct LdsTables {
     __device__ __forceinline__ uint32_t moved_by(uint32_t c, uint32_t k) const { return atomicAdd(&cnt[c], k << 16); }
 };
 
+// LDS tables that also record the member of a one-vertex class created by a
+// split, in the class's clast slot with flag bit 15 (positions stay below
+// 2^15 where this form is used; such a class ends where it starts). The
+// member never moves again (a one-position class cannot split) and the
+// position is not reused once it is numbered, so a recorded member stays
+// valid while its class lives. When the pivot empties the top class and the
+// candidate class below is such a class, its member is the next pivot's only
+// candidate and the selection skips matching class ids.
+struct LdsTablesSole : LdsTables {
+    static constexpr bool kSole = true;
+    static constexpr uint32_t kFlag = 0x8000u;
+    __device__ __forceinline__ uint32_t last(uint32_t c) const
+    {
+        const uint32_t r = clast[c];
+        return (r & kFlag) ? c : r;
+    }
+    __device__ __forceinline__ void set_sole(uint32_t c, uint32_t v) const { clast[c] = (uint16_t)(kFlag | v); }
+    __device__ __forceinline__ uint32_t slot(uint32_t c) const { return clast[c]; }
+};
+
 // The global form is read and written by one workgroup only (its team), so
 // every access has workgroup scope: atomics complete in the L2 of the CU's
 // own die and loads may be served by the CU's L1, which the same CU's
@@ -411,6 +432,7 @@ struct GlobalTables {
     LX_GLOBAL uint32_t *clast;
     LX_GLOBAL uint32_t *cnt;
     static constexpr bool kInLds = false;
+    static constexpr bool kSole = false;
     static constexpr int kScope = __HIP_MEMORY_SCOPE_WORKGROUP;
     __device__ GlobalTables(uint32_t *cl, uint32_t *ct) : clast(as_global(cl)), cnt(as_global(ct)) {}
     __device__ __forceinline__ uint32_t last(uint32_t c) const
@@ -769,6 +791,7 @@ __device__ __forceinline__ void lexbfs_team(const Team &tm, int n, const uint64_
         // neither, and the class start cleared below is U, above U - 1.
         constexpr int kQ = kPre / 8;
         uint64_t s_hi = 0ull, s_lo = 0ull;
+        uint32_t sole = 0u;  // recorded-member form: the clast slot of position U - 1
         uint4 cc[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) cc[q] = make_uint4(0u, 0u, 0u, 0u);
@@ -776,6 +799,7 @@ __device__ __forceinline__ void lexbfs_team(const Team &tm, int n, const uint64_
             const int pw = (U - 1) >> 6;
             s_hi = starts[pw];
             if (pw > 0) s_lo = starts[pw - 1];
+            if constexpr (Tabs::kSole) sole = tab.slot((uint32_t)(U - 1));
             if (K >= 8 && K <= kPre && owner) {
                 const uint4 *p = (const uint4 *)(cls + vbase);
 #pragma unroll
@@ -903,7 +927,12 @@ __device__ __forceinline__ void lexbfs_team(const Team &tm, int n, const uint64_
                 cand = tm.max_all(hi, red + par * 2 * NW) - 1u;
                 par ^= 1;
             }
-            if (K >= 8 && K <= kPre) {
+            if (Tabs::kSole && cand == (uint32_t)(U - 1) && (sole & 0x8000u)) {
+                // a one-vertex class with its member recorded: only the
+                // member's owner lane has a candidate
+                const uint32_t v = sole & 0x7FFFu;
+                top = (v >= (uint32_t)vbase && v < (uint32_t)(vbase + K)) ? (1ull << (v & 63)) & um : 0ull;
+            } else if (K >= 8 && K <= kPre) {
                 uint64_t mm = 0ull;
 #pragma unroll
                 for (int q = 0; q < kQ; q += 2)  // ids past the chunk: masked by um
@@ -999,6 +1028,8 @@ __device__ __forceinline__ void lexbfs_team(const Team &tm, int n, const uint64_
                     if (split) {
                         tab.set_last(C, nw - 1);
                         atomicOr((unsigned long long *)&starts[nw >> 6], 1ull << (nw & 63));
+                        if constexpr (Tabs::kSole)
+                            if (c == 1) tab.set_sole(nw, (uint32_t)y);  // y alone in its new class
                     }
                 }
             }
