@@ -167,6 +167,20 @@ def test_split_heavy_steps_smaller_teams(n, K):
     check_single(heavy_split_n(n, K), tag=f"heavy split n={n}, clique of {K}")
 
 
+@pytest.mark.parametrize("n,K", [(65536, 32), (16384, 64)])
+def test_split_heavy_steps_mcs_and_per_step(n, K):
+    """The heavy split graphs through the MCS order (1,024- and 512-lane
+    MCS kernels) and the per-step-launch form of LexBFS."""
+    g = heavy_split(K) if n == 65536 else heavy_split_n(n, K)
+    say(f"[parity] heavy split MCS n={n} K={K}")
+    ref = oracle.chordal_test(g, "mcs")
+    r = lx.chordal_test(lx.DeviceGraph.from_host(g, DEV), flags=lx.LEXBFS_FLAG_MCS)
+    assert np.array_equal(r.order.cpu().numpy(), ref.order), "MCS order"
+    assert np.array_equal(r.parent.cpu().numpy(), ref.parent), "MCS parent"
+    assert r.chordal == ref.chordal and r.witness == ref.witness and r.cycle_list == ref.cycle.tolist()
+    check_single(g, flags=lx.LEXBFS_FLAG_PER_STEP, tag=f"heavy split per-step n={n} K={K}")
+
+
 def test_batch_heavy_steps_every_tier():
     check_batch([heavy_split_n(n, K) for n, K in HEAVY_SMALLER], tag="heavy split graphs, n = 1,024 .. 32,768")
 
