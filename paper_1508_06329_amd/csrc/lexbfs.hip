@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep_single(GDesc g, int row
 {
     const int r0 = blockIdx.x * rows_per_block;
     const int r1 = min(g.n, r0 + rows_per_block);
-    sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, r0, r1, G, lg, g.failkey);
+    sweep_rows<true>(g.bits, g.W, g.wn, g.rank, g.parent, g.n, r0, r1, G, lg, g.failkey);
 }
 
 // Verdict, witness and certificate of one graph on a T-lane workgroup
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(T) void k_batch_large(const GDesc *__restrict__ gds
         G <<= 1;
         ++lg;
     }
-    sweep_rows(g.bits, g.W, g.wn, g.rank, g.parent, g.n, 0, g.n, G, lg, g.failkey);
+    sweep_rows<false>(g.bits, g.W, g.wn, g.rank, g.parent, g.n, 0, g.n, G, lg, g.failkey);
     tm.sync_mem();  // the failing rank visible to the certificate
     finish_graph(tm, g, flags, carve_finish(lds, g.wn, T / kWave));
 }
